@@ -1,0 +1,757 @@
+// Host runtime of libddpinn: argument validation, workspace layout, work
+// partitioning, hipGraph capture and the C ABI declared in include/ddpinn.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ddpinn.h"
+#include "ddpinn_internal.h"
+
+namespace ddp {
+hipError_t set_lds_limits(int bytes);
+}
+
+using namespace ddp;
+
+namespace {
+
+thread_local std::string g_err;
+
+pinn_status fail(pinn_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+pinn_status fail(pinn_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHECK(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(PINN_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int64_t nparams(int dim, int W, int H) {
+  const int64_t D = dim + 1;
+  return W * D + W + (int64_t)(H - 1) * ((int64_t)W * W + W) + D * W + D;
+}
+
+Shape make_shape(int dim, int W, int H) {
+  Shape sh{};
+  sh.dim = dim;
+  sh.D = dim + 1;
+  sh.W = W;
+  sh.H = H;
+  sh.Wp = (W + 15) / 16 * 16;
+  sh.NW = sh.Wp / 16;
+  sh.P = (int32_t)nparams(dim, W, H);
+  const int64_t Wp = sh.Wp, D = sh.D;
+  // packed offsets
+  int64_t o = 0;
+  for (int l = 1; l <= H + 1; ++l) {
+    const int64_t fi = (l == 1) ? D : W, fo = (l == H + 1) ? D : W;
+    sh.p_w[l] = o;
+    o += fo * fi;
+    sh.p_b[l] = o;
+    o += fo;
+  }
+  // fragment buffer
+  o = 0;
+  sh.f_hid = o; o += 2 * (int64_t)(H - 1) * Wp * Wp;
+  sh.f_w1 = o;  o += Wp * D;
+  sh.f_b = o;   o += (int64_t)H * Wp;
+  sh.f_wo = o;  o += D * Wp;
+  sh.f_bo = o;  o += 4;
+  sh.frag_floats = (o + 63) / 64 * 64;
+  // slab
+  o = 0;
+  sh.s_hid = o; o += (int64_t)(H - 1) * Wp * Wp;
+  sh.s_b = o;   o += (int64_t)H * Wp;
+  sh.s_w1 = o;  o += Wp * D;
+  sh.s_wo = o;  o += D * Wp;
+  sh.s_bo = o;  o += 4;
+  sh.s_loss = o; o += 8;
+  sh.slab_floats = (o + 63) / 64 * 64;
+  return sh;
+}
+
+struct Partition {
+  std::vector<Item> items;
+  std::vector<int32_t> wg_begin;   // n_wg + 1
+  std::vector<int32_t> seg_begin;  // n_sub + 1
+  int n_wg = 0, n_seg = 0;
+};
+
+// Tiles of one subdomain, collocation tiles first, then value tiles over
+// the concatenated [observation | ghost | anchor] list.
+void tiles_of(const pinn_subdomain& s, int sub, int tp, int tv, std::vector<Item>& out) {
+  for (int64_t st = 0; st < s.n_pde; st += tp)
+    out.push_back(Item{sub, ITEM_PDE, (int32_t)st, (int32_t)std::min<int64_t>(tp, s.n_pde - st), -1, 0, {0, 0}});
+  const int64_t nv = s.n_obs + s.n_gh + s.n_anc;
+  for (int64_t st = 0; st < nv; st += tv)
+    out.push_back(Item{sub, ITEM_VALUE, (int32_t)st, (int32_t)std::min<int64_t>(tv, nv - st), -1, 0, {0, 0}});
+}
+
+// Split a sorted item list into n_wg contiguous ranges and mark segments
+// (maximal runs of one subdomain inside one workgroup); slabs are numbered
+// from slab0.
+void partition(std::vector<Item>& items, int n_wg, int slab0, std::vector<int32_t>& wg_begin, int* n_seg) {
+  const int64_t n = (int64_t)items.size();
+  wg_begin.assign(n_wg + 1, 0);
+  for (int b = 0; b <= n_wg; ++b) wg_begin[b] = (int32_t)(n * b / n_wg);
+  int seg = slab0 - 1;
+  for (int b = 0; b < n_wg; ++b) {
+    for (int i = wg_begin[b]; i < wg_begin[b + 1]; ++i) {
+      const bool first = (i == wg_begin[b]) || items[i].sub != items[i - 1].sub;
+      const bool last = (i + 1 == wg_begin[b + 1]) || items[i].sub != items[i + 1].sub;
+      if (first) ++seg;
+      items[i].slab = seg;
+      items[i].flags = (first ? ITEM_FIRST : 0) | (last ? ITEM_LAST : 0);
+    }
+  }
+  *n_seg = seg + 1 - slab0;
+}
+
+}  // namespace
+
+struct pinn_ctx {
+  pinn_config cfg{};
+  Shape sh{};
+  int n_sub = 0;
+  std::vector<pinn_subdomain> subs;
+  int device = 0, num_cu = 0;
+  int tile_points = 16, value_points = 0;
+  int threads = 0;
+  int lds_floats = 0, qlds_floats = 0;
+  int step_occ = 1, query_occ = 1;
+  // grouped launch
+  int n_wg = 0, n_items = 0, n_seg = 0;
+  // per-subdomain launches
+  std::vector<int> ps_wg, ps_wgb_off;
+  int ps_items = 0, ps_seg = 0;
+  int n_slabs = 0;
+  int64_t stash_per_wg = 0;
+  // device regions inside the workspace
+  SubDev* d_subs = nullptr;
+  Item* d_items = nullptr;
+  int32_t* d_wg_begin = nullptr;
+  int32_t* d_seg_begin = nullptr;
+  Item* d_items_ps = nullptr;
+  int32_t* d_wgb_ps = nullptr;
+  int32_t* d_seg_ps = nullptr;
+  float* d_slabs = nullptr;
+  float* d_stash = nullptr;
+  float* d_frag = nullptr;
+  float* d_loss_ws = nullptr;
+  int32_t* d_flag = nullptr;
+  float* d_boxes = nullptr;
+  ExchangeItem* d_xitems = nullptr;
+  float** d_targets = nullptr;
+  int x_cap = 0;
+  std::vector<ExchangeItem> x_host;
+  std::vector<float*> x_targets_host;
+  bool x_pending = false;
+  float gmax[4] = {0, 0, 0, 0};
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipGraphNode_t n_reduce = nullptr;
+  ReduceArgs rargs{};
+  StepArgs sargs{};
+  PrepArgs pargs{};
+  // kernel timing (PINN_TIME_KERNEL)
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  int ev_used = 0;
+  double ev_folded_ms = 0.0;
+  int64_t ev_folded_n = 0;
+};
+
+namespace {
+constexpr int kEventPool = 1024;
+
+// wait for the recorded event pairs, add their durations to the folded sum
+pinn_status fold_events(pinn_ctx* c) {
+  for (int i = 0; i < c->ev_used; ++i) {
+    HIPCHECK(hipEventSynchronize(c->ev_stop[i]));
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]));
+    c->ev_folded_ms += ms;
+    c->ev_folded_n += 1;
+  }
+  c->ev_used = 0;
+  return PINN_OK;
+}
+
+pinn_status next_event_pair(pinn_ctx* c, hipEvent_t* a, hipEvent_t* b) {
+  if (c->ev_start.empty()) {
+    c->ev_start.resize(kEventPool);
+    c->ev_stop.resize(kEventPool);
+    for (int i = 0; i < kEventPool; ++i) {
+      HIPCHECK(hipEventCreate(&c->ev_start[i]));
+      HIPCHECK(hipEventCreate(&c->ev_stop[i]));
+    }
+  }
+  if (c->ev_used == kEventPool) {
+    pinn_status st = fold_events(c);
+    if (st != PINN_OK) return st;
+  }
+  *a = c->ev_start[c->ev_used];
+  *b = c->ev_stop[c->ev_used];
+  c->ev_used++;
+  return PINN_OK;
+}
+}  // namespace
+
+extern "C" {
+
+const char* pinn_last_error(void) { return g_err.c_str(); }
+
+int64_t pinn_num_params(int32_t dim, int32_t width, int32_t depth) {
+  if (dim < 2 || dim > 3 || width < 1 || depth < 1) return -1;
+  return nparams(dim, width, depth);
+}
+
+static pinn_status validate(const pinn_config* cfg, const pinn_subdomain* subs) {
+  if (!cfg) return fail(PINN_E_INVAL, "cfg is NULL");
+  if (cfg->dim != 2 && cfg->dim != 3) return fail(PINN_E_INVAL, "dim must be 2 or 3 (got %d)", cfg->dim);
+  if (cfg->width < 1) return fail(PINN_E_INVAL, "width must be >= 1");
+  if (cfg->width > kMaxWidth) return fail(PINN_E_UNSUPPORTED, "width %d > %d", cfg->width, kMaxWidth);
+  if (cfg->depth < 1) return fail(PINN_E_INVAL, "depth must be >= 1");
+  if (cfg->depth > kMaxDepth) return fail(PINN_E_UNSUPPORTED, "depth %d > %d", cfg->depth, kMaxDepth);
+  if (cfg->n_sub < 1 || cfg->n_sub > kMaxSub) return fail(PINN_E_INVAL, "n_sub must be in [1, %d]", kMaxSub);
+  if (cfg->activation != 0) return fail(PINN_E_UNSUPPORTED, "only tanh (activation 0) is supported");
+  if (!(std::isfinite(cfg->nu) && cfg->nu >= 0)) return fail(PINN_E_INVAL, "nu must be finite and >= 0");
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(cfg->lam[k])) return fail(PINN_E_INVAL, "lam[%d] not finite", k);
+  if (!(cfg->lr >= 0 && std::isfinite(cfg->lr))) return fail(PINN_E_INVAL, "lr must be finite and >= 0");
+  if (!(cfg->beta1 >= 0 && cfg->beta1 < 1 && cfg->beta2 >= 0 && cfg->beta2 < 1))
+    return fail(PINN_E_INVAL, "Adam betas must be in [0, 1)");
+  if (!(cfg->eps > 0)) return fail(PINN_E_INVAL, "Adam eps must be > 0");
+  if (cfg->tile_points != 0 && cfg->tile_points != 16 && cfg->tile_points != 32)
+    return fail(PINN_E_INVAL, "tile_points must be 0, 16 or 32");
+  if (cfg->blocks_per_cu < 0) return fail(PINN_E_INVAL, "blocks_per_cu must be >= 0");
+  if (cfg->max_query_points < 0 || cfg->max_query_points > (int64_t)INT32_MAX)
+    return fail(PINN_E_INVAL, "max_query_points out of range");
+  if (cfg->flags & ~PINN_GRAPH) return fail(PINN_E_INVAL, "unknown config flags 0x%x", cfg->flags);
+  if (!subs) return fail(PINN_E_INVAL, "subs is NULL");
+  const int D = cfg->dim + 1;
+  for (int s = 0; s < cfg->n_sub; ++s) {
+    const pinn_subdomain& d = subs[s];
+    if (!d.theta || !d.adam_m || !d.adam_v) return fail(PINN_E_INVAL, "sub %d: theta/adam_m/adam_v NULL", s);
+    const int64_t cnt[4] = {d.n_pde, d.n_obs, d.n_gh, d.n_anc};
+    for (int k = 0; k < 4; ++k)
+      if (cnt[k] < 0 || cnt[k] > (int64_t)INT32_MAX / 2)
+        return fail(PINN_E_INVAL, "sub %d: point count %d out of range", s, k);
+    if (d.n_obs + d.n_gh + d.n_anc > (int64_t)INT32_MAX / 2)
+      return fail(PINN_E_INVAL, "sub %d: too many value points", s);
+    if (d.n_pde && !d.pde_x) return fail(PINN_E_INVAL, "sub %d: pde_x NULL", s);
+    if (d.n_obs && (!d.obs_x || !d.obs_u)) return fail(PINN_E_INVAL, "sub %d: obs arrays NULL", s);
+    if (d.n_gh && (!d.gh_x || !d.gh_up || !d.gh_kind)) return fail(PINN_E_INVAL, "sub %d: ghost arrays NULL", s);
+    if (d.n_anc && (!d.anc_x || !d.anc_p)) return fail(PINN_E_INVAL, "sub %d: anchor arrays NULL", s);
+    for (int q = 0; q < D; ++q)
+      if (!(d.lo[q] <= d.hi[q])) return fail(PINN_E_INVAL, "sub %d: box lo > hi on axis %d", s, q);
+  }
+  return PINN_OK;
+}
+
+pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void* workspace,
+                        size_t* workspace_bytes, void* stream, pinn_ctx** out) {
+  g_err.clear();
+  pinn_status st = validate(cfg, subs);
+  if (st != PINN_OK) return st;
+  if (!workspace_bytes) return fail(PINN_E_INVAL, "workspace_bytes is NULL");
+  if (workspace && !out) return fail(PINN_E_INVAL, "out is NULL");
+  if (workspace && ((uintptr_t)workspace & 255)) return fail(PINN_E_INVAL, "workspace must be 256-byte aligned");
+
+  pinn_ctx tmp;
+  pinn_ctx* c = &tmp;
+  c->cfg = *cfg;
+  c->n_sub = cfg->n_sub;
+  c->sh = make_shape(cfg->dim, cfg->width, cfg->depth);
+  c->subs.assign(subs, subs + cfg->n_sub);
+  const Shape& sh = c->sh;
+
+  HIPCHECK(hipGetDevice(&c->device));
+  HIPCHECK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+  int max_lds = 0, optin = 0;
+  HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, c->device) == hipSuccess)
+    max_lds = std::max(max_lds, optin);
+  HIPCHECK(ddp::set_lds_limits(max_lds));
+
+  // tile shape: 32-point collocation tiles when they fit in LDS with at
+  // least the occupancy of 16-point tiles, unless fixed by the caller
+  c->threads = sh.NW * 64;
+  auto occ_of = [&](int tp, int* occ) -> pinn_status {
+    const int lf = step_lds_floats(sh, tp);
+    // 32-point tiles hold twice the registers: at most 4 waves (Wp <= 64)
+    if ((int64_t)lf * 4 > max_lds || (tp == 32 && c->threads > 256)) { *occ = 0; return PINN_OK; }
+    int nb = 0;
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel_ptr(sh.dim, tp), c->threads, (size_t)lf * 4));
+    *occ = nb;
+    return PINN_OK;
+  };
+  int occ16 = 0, occ32 = 0;
+  if ((st = occ_of(16, &occ16)) != PINN_OK) return st;
+  if ((st = occ_of(32, &occ32)) != PINN_OK) return st;
+  int tp = cfg->tile_points;
+  if (tp == 0) tp = 16;
+  const int occ = (tp == 32) ? occ32 : occ16;
+  if (occ < 1) return fail(PINN_E_UNSUPPORTED, "tile of %d points does not fit (LDS %d B)", tp, step_lds_floats(sh, tp) * 4);
+  c->tile_points = tp;
+  c->value_points = step_value_points(sh.dim, tp);
+  c->lds_floats = step_lds_floats(sh, tp);
+  c->step_occ = cfg->blocks_per_cu > 0 ? std::min(cfg->blocks_per_cu, occ) : occ;
+  c->qlds_floats = query_lds_floats(sh);
+  c->query_occ = std::max(1, std::min(max_lds / std::max(1, c->qlds_floats * 4), 2048 / c->threads));
+
+  // work items: grouped partition and per-subdomain partitions
+  std::vector<Item> items;
+  for (int s = 0; s < c->n_sub; ++s) tiles_of(c->subs[s], s, c->tile_points, c->value_points, items);
+  c->n_items = (int)items.size();
+  const int max_wg = c->num_cu * c->step_occ;
+  c->n_wg = std::max(1, std::min(c->n_items, max_wg));
+  std::vector<int32_t> wg_begin;
+  partition(items, c->n_wg, 0, wg_begin, &c->n_seg);
+  // segments are numbered in item order, which is sorted by subdomain, so
+  // each subdomain owns a contiguous slab range
+  std::vector<int32_t> seg_begin(c->n_sub + 1, 0);
+  for (size_t i = 0; i < items.size(); ++i)
+    if (items[i].flags & ITEM_FIRST) seg_begin[items[i].sub + 1]++;
+  for (int s = 0; s < c->n_sub; ++s) seg_begin[s + 1] += seg_begin[s];
+  std::vector<Item> items_ps;
+  std::vector<int32_t> wgb_ps, seg_ps(c->n_sub + 1, 0);
+  c->ps_wg.assign(c->n_sub, 0);
+  c->ps_wgb_off.assign(c->n_sub, 0);
+  {
+    int slab0 = 0;
+    for (int s = 0; s < c->n_sub; ++s) {
+      std::vector<Item> its;
+      tiles_of(c->subs[s], s, c->tile_points, c->value_points, its);
+      seg_ps[s] = slab0;
+      if (its.empty()) continue;
+      const int nw = std::max(1, std::min((int)its.size(), max_wg));
+      std::vector<int32_t> wb;
+      int nseg = 0;
+      partition(its, nw, slab0, wb, &nseg);
+      c->ps_wg[s] = nw;
+      c->ps_wgb_off[s] = (int)wgb_ps.size();
+      const int base = (int)items_ps.size();
+      for (int32_t v : wb) wgb_ps.push_back(v + base);
+      items_ps.insert(items_ps.end(), its.begin(), its.end());
+      slab0 += nseg;
+    }
+    seg_ps[c->n_sub] = slab0;
+    c->ps_seg = slab0;
+    c->ps_items = (int)items_ps.size();
+  }
+  c->n_slabs = std::max(std::max(c->n_seg, c->ps_seg), 1);
+  const int stash_wg = std::max(c->n_wg, 1);
+  const int NCB = (2 * sh.dim + 2) * (c->tile_points / 16);
+  c->stash_per_wg = (int64_t)sh.NW * sh.H * NCB * 256;
+
+  // exchange capacity: every ghost point in a half tile, plus one partial tile per face
+  int64_t xcap = 0;
+  const int xhalf = 16 * (2 * sh.dim + 2) / 2;
+  for (int s = 0; s < c->n_sub; ++s) xcap += (c->subs[s].n_gh + xhalf - 1) / xhalf;
+  xcap += 8LL * c->n_sub + 64;
+  c->x_cap = (int)std::min<int64_t>(xcap, 1 << 24);
+
+  // workspace layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  const size_t o_subs = take(sizeof(SubDev) * c->n_sub);
+  const size_t o_items = take(sizeof(Item) * std::max(c->n_items, 1));
+  const size_t o_wgb = take(sizeof(int32_t) * (c->n_wg + 1));
+  const size_t o_segb = take(sizeof(int32_t) * (c->n_sub + 1));
+  const size_t o_items_ps = take(sizeof(Item) * std::max(c->ps_items, 1));
+  const size_t o_wgb_ps = take(sizeof(int32_t) * std::max<size_t>(wgb_ps.size(), 1));
+  const size_t o_seg_ps = take(sizeof(int32_t) * (c->n_sub + 1));
+  const size_t o_slabs = take(sizeof(float) * (size_t)c->n_slabs * sh.slab_floats);
+  const size_t o_stash = take(sizeof(float) * (size_t)stash_wg * c->stash_per_wg);
+  const size_t o_frag = take(sizeof(float) * (size_t)c->n_sub * sh.frag_floats);
+  const size_t o_loss = take(sizeof(float) * 8 * c->n_sub);
+  const size_t o_flag = take(64);
+  const size_t o_boxes = take(sizeof(float) * 8 * c->n_sub);
+  const size_t o_xitems = take(sizeof(ExchangeItem) * c->x_cap);
+  const size_t o_targets = take(sizeof(float*) * c->n_sub);
+  const size_t total = off;
+  if (!workspace) {
+    *workspace_bytes = total;
+    return PINN_OK;
+  }
+  if (*workspace_bytes < total)
+    return fail(PINN_E_NOMEM, "workspace has %zu bytes, needs %zu", *workspace_bytes, total);
+
+  char* ws = (char*)workspace;
+  c->d_subs = (SubDev*)(ws + o_subs);
+  c->d_items = (Item*)(ws + o_items);
+  c->d_wg_begin = (int32_t*)(ws + o_wgb);
+  c->d_seg_begin = (int32_t*)(ws + o_segb);
+  c->d_items_ps = (Item*)(ws + o_items_ps);
+  c->d_wgb_ps = (int32_t*)(ws + o_wgb_ps);
+  c->d_seg_ps = (int32_t*)(ws + o_seg_ps);
+  c->d_slabs = (float*)(ws + o_slabs);
+  c->d_stash = (float*)(ws + o_stash);
+  c->d_frag = (float*)(ws + o_frag);
+  c->d_loss_ws = (float*)(ws + o_loss);
+  c->d_flag = (int32_t*)(ws + o_flag);
+  c->d_boxes = (float*)(ws + o_boxes);
+  c->d_xitems = (ExchangeItem*)(ws + o_xitems);
+  c->d_targets = (float**)(ws + o_targets);
+
+  // subdomain descriptors
+  std::vector<SubDev> sd(c->n_sub);
+  std::vector<float> boxes(8 * c->n_sub, 0.f);
+  for (int q = 0; q < 4; ++q) c->gmax[q] = -INFINITY;
+  for (int s = 0; s < c->n_sub; ++s) {
+    const pinn_subdomain& u = c->subs[s];
+    SubDev& d = sd[s];
+    std::memset(&d, 0, sizeof d);
+    d.theta = u.theta;
+    d.m = u.adam_m;
+    d.v = u.adam_v;
+    d.pde_x = u.pde_x;
+    d.obs_x = u.obs_x;
+    d.obs_u = u.obs_u;
+    d.gh_x = u.gh_x;
+    d.gh_up = u.gh_up;
+    d.gh_kind = u.gh_kind;
+    d.anc_x = u.anc_x;
+    d.anc_p = u.anc_p;
+    d.frag = c->d_frag + (size_t)s * sh.frag_floats;
+    d.n_pde = (int32_t)u.n_pde;
+    d.n_obs = (int32_t)u.n_obs;
+    d.n_gh = (int32_t)u.n_gh;
+    d.n_anc = (int32_t)u.n_anc;
+    for (int k = 0; k < 6; ++k) d.lam[k] = cfg->lam[k];
+    if (u.is_master) d.lam[3] = 0.f;   // master: no spatial ghost pressure term
+    d.inv_n[0] = u.n_pde ? 1.f / (float)u.n_pde : 0.f;
+    d.inv_n[1] = u.n_obs ? 1.f / (float)u.n_obs : 0.f;
+    d.inv_n[2] = u.n_gh ? 1.f / (float)u.n_gh : 0.f;
+    d.inv_n[3] = u.n_anc ? 1.f / (float)u.n_anc : 0.f;
+    for (int q = 0; q < 4; ++q) {
+      d.lo[q] = u.lo[q];
+      d.hi[q] = u.hi[q];
+      boxes[s * 8 + q] = u.lo[q];
+      boxes[s * 8 + 4 + q] = u.hi[q];
+      if (q <= cfg->dim) c->gmax[q] = std::max(c->gmax[q], u.hi[q]);
+    }
+    d.is_master = u.is_master ? 1 : 0;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(hipMemcpyAsync(c->d_subs, sd.data(), sizeof(SubDev) * c->n_sub, hipMemcpyHostToDevice, s));
+  if (c->n_items) HIPCHECK(hipMemcpyAsync(c->d_items, items.data(), sizeof(Item) * c->n_items, hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(c->d_wg_begin, wg_begin.data(), sizeof(int32_t) * (c->n_wg + 1), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(c->d_seg_begin, seg_begin.data(), sizeof(int32_t) * (c->n_sub + 1), hipMemcpyHostToDevice, s));
+  if (c->ps_items) HIPCHECK(hipMemcpyAsync(c->d_items_ps, items_ps.data(), sizeof(Item) * c->ps_items, hipMemcpyHostToDevice, s));
+  if (!wgb_ps.empty()) HIPCHECK(hipMemcpyAsync(c->d_wgb_ps, wgb_ps.data(), sizeof(int32_t) * wgb_ps.size(), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(c->d_seg_ps, seg_ps.data(), sizeof(int32_t) * (c->n_sub + 1), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(c->d_boxes, boxes.data(), sizeof(float) * 8 * c->n_sub, hipMemcpyHostToDevice, s));
+
+  // kernel argument blocks
+  c->pargs.sh = sh;
+  c->pargs.subs = c->d_subs;
+  c->pargs.n_sub = c->n_sub;
+  c->sargs.sh = sh;
+  c->sargs.subs = c->d_subs;
+  c->sargs.items = c->d_items;
+  c->sargs.wg_begin = c->d_wg_begin;
+  c->sargs.slabs = c->d_slabs;
+  c->sargs.stash = c->d_stash;
+  c->sargs.stash_per_wg = c->stash_per_wg;
+  c->sargs.nu = (float)cfg->nu;
+  c->sargs.lds_floats = c->lds_floats;
+  c->rargs.sh = sh;
+  c->rargs.subs = c->d_subs;
+  c->rargs.seg_begin = c->d_seg_begin;
+  c->rargs.slabs = c->d_slabs;
+  c->rargs.loss_ws = c->d_loss_ws;
+  c->rargs.n_sub = c->n_sub;
+  c->rargs.lr = cfg->lr;
+  c->rargs.beta1 = cfg->beta1;
+  c->rargs.beta2 = cfg->beta2;
+  c->rargs.eps = cfg->eps;
+
+  HIPCHECK(launch_prep(c->pargs, s));
+
+  if (cfg->flags & PINN_GRAPH) {
+    hipGraph_t gr;
+    HIPCHECK(hipGraphCreate(&gr, 0));
+    hipGraphNode_t n1, n2, n3, n4;
+    hipKernelNodeParams kp{};
+    void* pa[] = {&c->pargs};
+    grid_prep(c->pargs, &kp.gridDim, &kp.blockDim);
+    kp.func = (void*)prep_kernel_ptr();
+    kp.kernelParams = pa;
+    kp.sharedMemBytes = 0;
+    HIPCHECK(hipGraphAddKernelNode(&n1, gr, nullptr, 0, &kp));
+    void* sa[] = {&c->sargs};
+    hipKernelNodeParams ks{};
+    ks.func = (void*)step_kernel_ptr(sh.dim, c->tile_points);
+    ks.gridDim = dim3(c->n_wg);
+    ks.blockDim = dim3(c->threads);
+    ks.sharedMemBytes = (unsigned)(c->lds_floats * 4);
+    ks.kernelParams = sa;
+    HIPCHECK(hipGraphAddKernelNode(&n2, gr, &n1, 1, &ks));
+    c->rargs.t = 1;
+    c->rargs.update = 0;
+    void* ra[] = {&c->rargs};
+    hipKernelNodeParams kr{};
+    grid_reduce(c->rargs, &kr.gridDim, &kr.blockDim);
+    kr.func = (void*)reduce_kernel_ptr();
+    kr.kernelParams = ra;
+    HIPCHECK(hipGraphAddKernelNode(&n3, gr, &n2, 1, &kr));
+    HIPCHECK(hipGraphAddKernelNode(&n4, gr, &n3, 1, &kp));
+    c->graph = gr;
+    c->n_reduce = n3;
+    HIPCHECK(hipGraphInstantiate(&c->gexec, gr, nullptr, nullptr, 0));
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+
+  pinn_ctx* h = new pinn_ctx(std::move(tmp));
+  *out = h;
+  *workspace_bytes = total;
+  return PINN_OK;
+}
+
+static pinn_status run_step_eager(pinn_ctx* c, bool per_sub, bool timed, hipStream_t s) {
+  HIPCHECK(launch_prep(c->pargs, s));
+  ReduceArgs ra = c->rargs;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    pinn_status st = next_event_pair(c, &e0, &e1);
+    if (st != PINN_OK) return st;
+    HIPCHECK(hipEventRecord(e0, s));
+  }
+  if (!per_sub) {
+    if (c->n_items) HIPCHECK(launch_step(c->sargs, c->tile_points, c->n_wg, s));
+  } else {
+    // one plain launch per subdomain over its own partition and slabs
+    for (int k = 0; k < c->n_sub; ++k) {
+      if (!c->ps_wg[k]) continue;
+      StepArgs a = c->sargs;
+      a.items = c->d_items_ps;
+      a.wg_begin = c->d_wgb_ps + c->ps_wgb_off[k];
+      HIPCHECK(launch_step(a, c->tile_points, c->ps_wg[k], s));
+    }
+    ra.seg_begin = c->d_seg_ps;
+  }
+  if (timed) HIPCHECK(hipEventRecord(e1, s));
+  HIPCHECK(launch_reduce(ra, s));
+  HIPCHECK(launch_prep(c->pargs, s));
+  return PINN_OK;
+}
+
+pinn_status pinn_step(pinn_ctx* c, int64_t t, uint32_t flags, float* loss_out, float* grad_out, void* stream) {
+  g_err.clear();
+  if (!c) return fail(PINN_E_INVAL, "ctx is NULL");
+  if (flags & ~(PINN_NO_UPDATE | PINN_CHECK_FINITE | PINN_PER_SUBDOMAIN | PINN_TIME_KERNEL))
+    return fail(PINN_E_INVAL, "unknown step flags 0x%x", flags);
+  const bool update = !(flags & PINN_NO_UPDATE);
+  if (update && t < 1) return fail(PINN_E_INVAL, "Adam step t must be >= 1 (got %lld)", (long long)t);
+  hipStream_t s = (hipStream_t)stream;
+  const bool per_sub = flags & PINN_PER_SUBDOMAIN;
+  c->rargs.t = update ? t : 1;
+  c->rargs.update = update ? 1 : 0;
+  c->rargs.loss_out = loss_out;
+  c->rargs.grad_out = grad_out;
+  const bool timed = flags & PINN_TIME_KERNEL;
+  if (!per_sub && !timed && c->gexec) {
+    void* ra[] = {&c->rargs};
+    hipKernelNodeParams kr{};
+    grid_reduce(c->rargs, &kr.gridDim, &kr.blockDim);
+    kr.func = (void*)reduce_kernel_ptr();
+    kr.kernelParams = ra;
+    HIPCHECK(hipGraphExecKernelNodeSetParams(c->gexec, c->n_reduce, &kr));
+    HIPCHECK(hipGraphLaunch(c->gexec, s));
+  } else {
+    pinn_status st = run_step_eager(c, per_sub, timed, s);
+    if (st != PINN_OK) return st;
+  }
+  if (flags & PINN_CHECK_FINITE) {
+    std::vector<float> L(8 * c->n_sub);
+    HIPCHECK(hipMemcpyAsync(L.data(), c->d_loss_ws, sizeof(float) * L.size(), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    for (size_t k = 0; k < L.size(); ++k)
+      if (!std::isfinite(L[k])) return fail(PINN_E_NONFINITE, "loss of subdomain %zu is not finite", k / 8);
+  }
+  return PINN_OK;
+}
+
+size_t pinn_query_scratch_bytes(const pinn_ctx* c, int64_t n) {
+  if (!c || n < 0) return 0;
+  return align256(4 * (size_t)n) * 2 + align256(4 * (size_t)(c->n_sub + 1)) * 3;
+}
+
+pinn_status pinn_query(pinn_ctx* c, const float* x, int64_t n, int32_t sub, uint32_t what, float* out,
+                       void* scratch, size_t scratch_bytes, void* stream) {
+  g_err.clear();
+  if (!c) return fail(PINN_E_INVAL, "ctx is NULL");
+  if (n < 0) return fail(PINN_E_INVAL, "n < 0");
+  if (what > PINN_Q_RESIDUAL) return fail(PINN_E_INVAL, "unknown query kind %u", what);
+  if (what == PINN_Q_UVPW && c->sh.dim != 2) return fail(PINN_E_INVAL, "PINN_Q_UVPW needs dim 2");
+  if (sub < -1 || sub >= c->n_sub) return fail(PINN_E_INVAL, "sub %d out of range", sub);
+  if (n == 0) return PINN_OK;
+  if (!x || !out) return fail(PINN_E_INVAL, "x or out is NULL");
+  if (n > (int64_t)INT32_MAX) return fail(PINN_E_INVAL, "n too large");
+  hipStream_t s = (hipStream_t)stream;
+  const Shape& sh = c->sh;
+  QueryArgs qa{};
+  qa.sh = sh;
+  qa.subs = c->d_subs;
+  qa.x = x;
+  qa.out = out;
+  qa.n = n;
+  qa.sub = sub;
+  qa.n_sub = c->n_sub;
+  qa.what = (int32_t)what;
+  qa.nu = (float)c->cfg.nu;
+  qa.lds_floats = c->qlds_floats;
+  const int CF = 2 * sh.dim + 2;
+  const int npts = (what == PINN_Q_VALUE) ? 16 * CF : (what == PINN_Q_UVPW ? 16 * CF / (sh.dim + 1) : 16);
+  const int max_wg = c->num_cu * c->query_occ;
+  if (sub >= 0) {
+    const int64_t tiles = (n + npts - 1) / npts;
+    HIPCHECK(launch_query(qa, (int)std::min<int64_t>(tiles, max_wg), s));
+    return PINN_OK;
+  }
+  if (n > c->cfg.max_query_points)
+    return fail(PINN_E_BUDGET, "routed query of %lld points exceeds max_query_points %lld", (long long)n,
+                (long long)c->cfg.max_query_points);
+  const size_t need = pinn_query_scratch_bytes(c, n);
+  if (!scratch || scratch_bytes < need) return fail(PINN_E_NOMEM, "query scratch needs %zu bytes", need);
+  if ((uintptr_t)scratch & 255) return fail(PINN_E_INVAL, "scratch must be 256-byte aligned");
+  char* p = (char*)scratch;
+  RouteArgs ra{};
+  ra.x = x;
+  ra.n = n;
+  ra.boxes = c->d_boxes;
+  for (int q = 0; q < 4; ++q) ra.gmax[q] = c->gmax[q];
+  ra.n_sub = c->n_sub;
+  ra.D = sh.D;
+  const int out_cols = (what == PINN_Q_UVPW) ? 4 : (what == PINN_Q_CHANNELS ? CF * sh.D : sh.D);
+  ra.out_cols = out_cols;
+  ra.sub_id = (int32_t*)p; p += align256(4 * (size_t)n);
+  ra.perm = (int32_t*)p;   p += align256(4 * (size_t)n);
+  ra.counts = (int32_t*)p; p += align256(4 * (size_t)(c->n_sub + 1));
+  ra.cursor = (int32_t*)p; p += align256(4 * (size_t)(c->n_sub + 1));
+  ra.offsets = (int32_t*)p;
+  ra.out = out;
+  HIPCHECK(launch_route(ra, s));
+  qa.perm = ra.perm;
+  qa.counts = ra.counts;
+  qa.offsets = ra.offsets;
+  const int64_t tiles = (n + npts - 1) / npts + c->n_sub;
+  HIPCHECK(launch_query(qa, (int)std::min<int64_t>(tiles, max_wg), s));
+  return PINN_OK;
+}
+
+pinn_status pinn_exchange(pinn_ctx* c, const pinn_face* faces, int32_t n_faces, const float* x_anc,
+                          float* const* targets, void* stream) {
+  g_err.clear();
+  if (!c) return fail(PINN_E_INVAL, "ctx is NULL");
+  if (n_faces < 0 || (n_faces && (!faces || !targets))) return fail(PINN_E_INVAL, "bad faces/targets");
+  if (!x_anc) return fail(PINN_E_INVAL, "x_anc is NULL");
+  const Shape& sh = c->sh;
+  const int NCOL = 16 * (2 * sh.dim + 2);
+  std::vector<ExchangeItem> its;
+  for (int f = 0; f < n_faces; ++f) {
+    const pinn_face& fc = faces[f];
+    if (fc.a < 0 || fc.a >= c->n_sub || fc.b < 0 || fc.b >= c->n_sub)
+      return fail(PINN_E_INVAL, "face %d: subdomain out of range", f);
+    if (fc.first < 0 || fc.count < 0 || fc.first + fc.count > c->subs[fc.a].n_gh)
+      return fail(PINN_E_INVAL, "face %d: ghost range outside subdomain %d", f, fc.a);
+    if (!targets[fc.a]) return fail(PINN_E_INVAL, "face %d: targets[%d] is NULL", f, fc.a);
+    const int paired = c->subs[fc.b].is_master ? 1 : 0;
+    const int tp = paired ? NCOL / 2 : NCOL;
+    for (int64_t st = 0; st < fc.count; st += tp)
+      its.push_back(ExchangeItem{fc.a, fc.b, (int32_t)(fc.first + st),
+                                 (int32_t)std::min<int64_t>(tp, fc.count - st), paired, {0, 0, 0}});
+  }
+  if ((int)its.size() > c->x_cap) return fail(PINN_E_NOMEM, "exchange needs %zu tiles > capacity %d", its.size(), c->x_cap);
+  if (its.empty()) return PINN_OK;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<float*> tg(targets, targets + c->n_sub);
+  const bool same = its.size() == c->x_host.size() &&
+                    std::memcmp(its.data(), c->x_host.data(), its.size() * sizeof(ExchangeItem)) == 0 &&
+                    tg == c->x_targets_host;
+  if (!same) {
+    if (c->x_pending) HIPCHECK(hipDeviceSynchronize());
+    c->x_host = its;
+    c->x_targets_host = tg;
+    HIPCHECK(hipMemcpyAsync(c->d_xitems, c->x_host.data(), sizeof(ExchangeItem) * its.size(), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(c->d_targets, c->x_targets_host.data(), sizeof(float*) * c->n_sub, hipMemcpyHostToDevice, s));
+    c->x_pending = true;
+  }
+  ExchangeArgs ea{};
+  ea.sh = sh;
+  ea.subs = c->d_subs;
+  ea.items = c->d_xitems;
+  ea.n_items = (int32_t)its.size();
+  ea.lds_floats = c->qlds_floats;
+  ea.targets = c->d_targets;
+  for (int q = 0; q < sh.dim; ++q) ea.x_anc[q] = x_anc[q];
+  HIPCHECK(launch_exchange(ea, (int)std::min<int64_t>((int64_t)its.size(), (int64_t)c->num_cu * c->query_occ), s));
+  return PINN_OK;
+}
+
+pinn_status pinn_kernel_time(pinn_ctx* c, double* total_ms, int64_t* launches) {
+  g_err.clear();
+  if (!c || !total_ms || !launches) return fail(PINN_E_INVAL, "NULL argument");
+  pinn_status st = fold_events(c);
+  if (st != PINN_OK) return st;
+  *total_ms = c->ev_folded_ms;
+  *launches = c->ev_folded_n;
+  c->ev_folded_ms = 0.0;
+  c->ev_folded_n = 0;
+  return PINN_OK;
+}
+
+pinn_status pinn_refresh(pinn_ctx* c, void* stream) {
+  g_err.clear();
+  if (!c) return fail(PINN_E_INVAL, "ctx is NULL");
+  HIPCHECK(launch_prep(c->pargs, (hipStream_t)stream));
+  return PINN_OK;
+}
+
+pinn_status pinn_get_launch_info(const pinn_ctx* c, pinn_launch_info* info) {
+  if (!c || !info) return fail(PINN_E_INVAL, "NULL argument");
+  info->tile_points = c->tile_points;
+  info->value_points = c->value_points;
+  info->n_wg = c->n_wg;
+  info->n_items = c->n_items;
+  info->n_segments = c->n_seg;
+  info->threads = c->threads;
+  info->lds_bytes = (int64_t)c->lds_floats * 4;
+  info->stash_bytes = (int64_t)c->n_wg * c->stash_per_wg * 4;
+  info->slab_floats = c->sh.slab_floats;
+  return PINN_OK;
+}
+
+pinn_status pinn_destroy(pinn_ctx* c) {
+  g_err.clear();
+  if (!c) return PINN_OK;
+  hipError_t e = hipDeviceSynchronize();
+  for (hipEvent_t ev : c->ev_start) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : c->ev_stop) (void)hipEventDestroy(ev);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  delete c;
+  if (e != hipSuccess) return fail(PINN_E_DEVICE, "device error at destroy: %s", hipGetErrorString(e));
+  return PINN_OK;
+}
+
+}  // extern "C"

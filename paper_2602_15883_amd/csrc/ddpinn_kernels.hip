@@ -1,0 +1,1133 @@
+// HIP kernels for gfx950 (MI355X) of the fused subdomain training step of
+// domain-decomposed PINN flow reconstruction (arXiv 2602.15883).
+//
+// Method (section 2.1, 2.2): a tanh MLP local expert (x, t) -> (u, p); the
+// Navier-Stokes residuals r1..r4 need d/dx_j, d/dt and d2/dx_j^2 of every
+// output, which the forward pass carries as extra "channels" through every
+// layer (chain rule of tanh); losses L_obs, L_PDE, L_gh_u, L_gh_p (space and
+// time parts) and the optional anchor term; hand-written adjoint; Adam
+// (Algorithm 1, optimizer step).
+//
+// Work decomposition
+//   A tile holds NCB column blocks of 16 columns.  A collocation tile has
+//   16*PBP points and one column block per (channel, 16 points); a value tile
+//   (observation, ghost or anchor points, value channel only) has 16*NCB
+//   points.  A workgroup of Wp/16 waves processes one tile at a time; wave w
+//   owns neurons [16w, 16w+16) of every layer.
+//
+//   Each hidden layer is Z = W_l H (all channels at once, N = 16*NCB columns)
+//   on FP32 MFMA 16x16x4.  The A operand (weights) streams from a
+//   fragment-ordered copy in global memory (L2 resident); the B operand
+//   (activations) is staged in LDS.  The tanh chain rule runs in registers on
+//   the accumulator fragment: lane (g, j) holds rows 16w+4g+i (i = 0..3) of
+//   column 16cb+j, so every channel of a (neuron, point) pair sits in one lane.
+//
+//   Backward: pre-activations z of every layer are stashed per tile in a
+//   per-workgroup global ring; the adjoint recomputes tanh and its
+//   derivatives from them.  dW_l = Zbar H_{l-1}^T (K = columns) and
+//   Hbar_{l-1} = W_l^T Zbar run on MFMA.  Each workgroup accumulates its
+//   gradient contribution in a private slab (one per (workgroup, subdomain)
+//   segment); a second kernel sums the slabs in a fixed order and applies
+//   Adam.  No float atomics: results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "ddpinn_internal.h"
+
+namespace ddp {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+enum : int { M_PDE = 0, M_VALUE = 1, M_GRAD = 2 };
+
+__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ v4f zero4() { return v4f{0.f, 0.f, 0.f, 0.f}; }
+
+// Channel layout of a tile in a given mode.
+//   M_PDE  : CM = 2d+2 channels: 0 value, 1..d d/dx_j, d+1 d/dt, d+2..2d+1 d2/dx_j^2
+//   M_GRAD : CM = d+1 channels: 0 value, 1..d d/dx_j
+//   M_VALUE: CM = 1
+// Column block of (channel c, point block pb) = c*NPB + pb.
+template <int DIM, int NCB, int MODE>
+struct ModeCfg {
+  static constexpr int CF = 2 * DIM + 2;
+  static constexpr int CM = MODE == M_PDE ? CF : (MODE == M_VALUE ? 1 : DIM + 1);
+  static constexpr int NPB = NCB / CM;
+  static constexpr int NPTS = 16 * NPB;
+  static_assert(NCB % CM == 0, "column blocks must hold whole channel sets");
+};
+
+// ---------------------------------------------------------------------------
+// activation: z -> h with the chain rule, in place on accumulator fragments
+//   h = tanh(z0); h_j = s1 z_j; h_jj = s2 z_j^2 + s1 z_jj
+//   s1 = 1 - tanh^2, s2 = -2 tanh s1
+// ---------------------------------------------------------------------------
+template <int DIM, int NCB, int MODE>
+__device__ __forceinline__ void act_forward(v4f (&a)[NCB]) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int NPB = M::NPB;
+#pragma unroll
+  for (int pb = 0; pb < NPB; ++pb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float s = tanhf(a[pb][i]);
+      const float s1 = 1.f - s * s;
+      if constexpr (MODE == M_PDE) {
+        const float s2 = -2.f * s * s1;
+#pragma unroll
+        for (int jj = 0; jj < DIM; ++jj) {
+          const float z1 = a[(1 + jj) * NPB + pb][i];
+          const float z2 = a[(DIM + 2 + jj) * NPB + pb][i];
+          a[(DIM + 2 + jj) * NPB + pb][i] = s2 * z1 * z1 + s1 * z2;
+        }
+#pragma unroll
+        for (int jj = 0; jj <= DIM; ++jj) a[(1 + jj) * NPB + pb][i] *= s1;
+      } else if constexpr (MODE == M_GRAD) {
+#pragma unroll
+        for (int jj = 0; jj < DIM; ++jj) a[(1 + jj) * NPB + pb][i] *= s1;
+      }
+      a[pb][i] = s;
+    }
+  }
+}
+
+// Adjoint of act_forward: hb (dL/dh) -> dL/dz in place; zs holds z.
+//   zbar_jj = s1 hbar_jj
+//   zbar_j  = s1 hbar_j + 2 s2 z_j hbar_jj      (spatial j; time: s1 hbar_t)
+//   zbar_0  = s1 hbar_0 + s2 sum_j z_j hbar_j + sum_j (s3 z_j^2 + s2 z_jj) hbar_jj
+//   s3 = 2 s1 (3 tanh^2 - 1)
+template <int DIM, int NCB, int MODE>
+__device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int NPB = M::NPB;
+#pragma unroll
+  for (int pb = 0; pb < NPB; ++pb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float s = tanhf(zs[pb][i]);
+      const float s1 = 1.f - s * s;
+      if constexpr (MODE == M_PDE) {
+        const float s2 = -2.f * s * s1;
+        const float s3 = 2.f * s1 * (3.f * s * s - 1.f);
+        float z0b = s1 * hb[pb][i];
+#pragma unroll
+        for (int jj = 0; jj <= DIM; ++jj) {
+          const int c = (1 + jj) * NPB + pb;
+          const float h1 = hb[c][i];
+          z0b += s2 * zs[c][i] * h1;
+          hb[c][i] = s1 * h1;
+        }
+#pragma unroll
+        for (int jj = 0; jj < DIM; ++jj) {
+          const int c1 = (1 + jj) * NPB + pb, c2 = (DIM + 2 + jj) * NPB + pb;
+          const float h2 = hb[c2][i];
+          const float z1 = zs[c1][i], z2 = zs[c2][i];
+          hb[c2][i] = s1 * h2;
+          hb[c1][i] += 2.f * s2 * z1 * h2;
+          z0b += (s3 * z1 * z1 + s2 * z2) * h2;
+        }
+        hb[pb][i] = z0b;
+      } else {
+        hb[pb][i] *= s1;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// GEMMs on FP32 MFMA 16x16x4
+//
+// K index of MFMA step s in lane group g (g = lane/16): kmap(s, g) = g*Wq + s
+// with Wq = Wp/4, so that 4 consecutive steps of one lane read 4 contiguous
+// floats (one ds_read_b128).  The weight fragments are laid out with the same
+// map:  frag[((w*K4 + s4)*64 + lane)*4 + q] = W[16w + lane%16][kmap(4 s4 + q, lane/16)].
+// ---------------------------------------------------------------------------
+
+// acc[cb] += A(16 rows of this wave) * B(LDS [16*NCB cols][S], K = Wp)
+template <int NCB>
+__device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const float* bufB,
+                                          int S, int K4, int g, int j, int lane,
+                                          v4f (&acc)[NCB]) {
+  const float* bb = bufB + j * S + g * (4 * K4);
+  const v4f* ap = reinterpret_cast<const v4f*>(afrag) + lane;
+#pragma unroll 2
+  for (int s4 = 0; s4 < K4; ++s4) {
+    const v4f a = ap[s4 * 64];
+    v4f b[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      b[cb] = *reinterpret_cast<const v4f*>(bb + cb * 16 * S + 4 * s4);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[q], b[cb][q], acc[cb]);
+  }
+}
+
+// dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col]
+//   Zbar from bufG ([col][neuron], stride S); Hprev from bufHb ([neuron][col], stride S2)
+//   K index of step s in lane group g: g*4*NCB + s
+template <int NCB>
+__device__ __forceinline__ void gemm_dw(const float* bufG, int S, const float* bufHb, int S2,
+                                        int w, int g, int j, int nb0, int nnb, v4f (&dw)[4]) {
+  const float* ab = bufG + (g * 4 * NCB) * S + 16 * w + j;
+  const float* bb = bufHb + (16 * nb0 + j) * S2 + g * 4 * NCB;
+#pragma unroll 2
+  for (int s4 = 0; s4 < NCB; ++s4) {
+    float a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) a[q] = ab[(4 * s4 + q) * S];
+    v4f b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      b[t] = (t < nnb) ? *reinterpret_cast<const v4f*>(bb + t * 16 * S2 + 4 * s4) : zero4();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        if (t < nnb) dw[t] = mfma4(a[q], b[t][q], dw[t]);
+  }
+}
+
+// sum over the 16 lanes of a lane group (same g)
+__device__ __forceinline__ float sum16(float v) {
+  v += __shfl_xor(v, 8, 16);
+  v += __shfl_xor(v, 4, 16);
+  v += __shfl_xor(v, 2, 16);
+  v += __shfl_xor(v, 1, 16);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// shared forward pieces
+// ---------------------------------------------------------------------------
+
+// input layer: z0 = W1 xi + b1; z_j = W1[:, j] (first-derivative channels);
+// second-derivative channels start at 0.  xin: LDS [points][D].
+template <int DIM, int NCB, int MODE>
+__device__ __forceinline__ void input_layer(v4f (&a)[NCB], const float* __restrict__ W1p,
+                                            const float* __restrict__ b1p, const float* xin,
+                                            int w, int g, int j) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int D = DIM + 1, NPB = M::NPB;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * w + 4 * g + i;
+    float wr[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) wr[q] = W1p[r * D + q];
+    const float br = b1p[r];
+#pragma unroll
+    for (int pb = 0; pb < NPB; ++pb) {
+      const float* xp = xin + (16 * pb + j) * D;
+      float z = br;
+#pragma unroll
+      for (int q = 0; q < D; ++q) z += wr[q] * xp[q];
+      a[pb][i] = z;
+      if constexpr (MODE == M_PDE) {
+#pragma unroll
+        for (int jj = 0; jj <= DIM; ++jj) a[(1 + jj) * NPB + pb][i] = wr[jj];
+#pragma unroll
+        for (int jj = 0; jj < DIM; ++jj) a[(DIM + 2 + jj) * NPB + pb][i] = 0.f;
+      } else if constexpr (MODE == M_GRAD) {
+#pragma unroll
+        for (int jj = 0; jj < DIM; ++jj) a[(1 + jj) * NPB + pb][i] = wr[jj];
+      }
+    }
+  }
+}
+
+// store an accumulator fragment into the forward LDS layout [col][neuron]
+template <int NCB>
+__device__ __forceinline__ void store_fwd(float* buf, int S, const v4f (&a)[NCB], int w, int g, int j) {
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+    *reinterpret_cast<v4f*>(buf + (16 * cb + j) * S + 16 * w + 4 * g) = a[cb];
+}
+
+// add the bias to the value-channel column blocks
+template <int NCB, int NPB>
+__device__ __forceinline__ void add_bias(v4f (&a)[NCB], const float* __restrict__ b, int w, int g) {
+  const v4f bv = *reinterpret_cast<const v4f*>(b + 16 * w + 4 * g);
+#pragma unroll
+  for (int pb = 0; pb < NPB; ++pb) a[pb] += bv;
+}
+
+// output layer: ys[o][col] = W_{H+1}[o] . h[col] (+ b_{H+1}[o] on value columns)
+template <int DIM, int NCB, int MODE>
+__device__ __forceinline__ void output_layer(const float* bufH, int S, int Wp,
+                                             const float* __restrict__ Wop, const float* __restrict__ bop,
+                                             float* ys, int tid, int nthr) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int D = DIM + 1, NCOL = 16 * NCB;
+  for (int idx = tid; idx < D * NCOL; idx += nthr) {
+    const int o = idx / NCOL, col = idx - o * NCOL;
+    const float* hr = bufH + col * S;
+    const float* wo = Wop + o * Wp;
+    float acc = 0.f;
+    for (int n = 0; n < Wp; n += 4) {
+      const v4f h4 = *reinterpret_cast<const v4f*>(hr + n);
+      const v4f w4 = *reinterpret_cast<const v4f*>(wo + n);
+      acc += h4[0] * w4[0];
+      acc += h4[1] * w4[1];
+      acc += h4[2] * w4[2];
+      acc += h4[3] * w4[3];
+    }
+    if (col < 16 * M::NPB) acc += bop[o];
+    ys[o * NCOL + col] = acc;
+  }
+}
+
+// Navier-Stokes residuals r1..r_{d+1} (section 2.1) from the channel stack of
+// one point; Y(c, o) = output o of channel c.
+template <int DIM, typename F>
+__device__ __forceinline__ void residuals(F Y, float nu, float (&r)[DIM + 1]) {
+#pragma unroll
+  for (int i = 0; i < DIM; ++i) {
+    float conv = 0.f, lap = 0.f;
+#pragma unroll
+    for (int jj = 0; jj < DIM; ++jj) {
+      conv += Y(0, jj) * Y(1 + jj, i);
+      lap += Y(DIM + 2 + jj, i);
+    }
+    r[i] = Y(1 + DIM, i) + conv + Y(1 + i, DIM) - nu * lap;
+  }
+  float div = 0.f;
+#pragma unroll
+  for (int jj = 0; jj < DIM; ++jj) div += Y(1 + jj, jj);
+  r[DIM] = div;
+}
+
+// ---------------------------------------------------------------------------
+// LDS plan of the step kernel (floats)
+// ---------------------------------------------------------------------------
+struct StepLds {
+  int S, S2, NCOL;
+  int bufH, bufG, ys, yb, xin, acc1, dbacc, red, total;
+};
+
+__host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB) {
+  StepLds L;
+  L.NCOL = 16 * NCB;
+  L.S = Wp + 4;
+  L.S2 = L.NCOL + 4;
+  const int hsz = (L.NCOL * L.S > Wp * L.S2) ? L.NCOL * L.S : Wp * L.S2;
+  int o = 0;
+  L.bufH = o; o += (hsz + 3) & ~3;
+  L.bufG = o; o += (L.NCOL * L.S + 3) & ~3;
+  L.ys = o;   o += (D * L.NCOL + 3) & ~3;
+  L.yb = o;   o += (D * L.NCOL + 3) & ~3;
+  L.xin = o;  o += (L.NCOL * D + 3) & ~3;
+  L.acc1 = o; o += (Wp * D + 3) & ~3;
+  L.dbacc = o; o += (H * Wp + 3) & ~3;
+  L.red = o;  o += 64;
+  L.total = o;
+  return L;
+}
+
+// ---------------------------------------------------------------------------
+// Fused step kernel: persistent over this workgroup's item range.
+// ---------------------------------------------------------------------------
+template <int DIM, int PBP>
+__global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepArgs args) {
+  constexpr int D = DIM + 1;
+  constexpr int CF = 2 * DIM + 2;
+  constexpr int NCB = CF * PBP;
+  constexpr int NCOL = 16 * NCB;
+  using MP = ModeCfg<DIM, NCB, M_PDE>;
+  using MV = ModeCfg<DIM, NCB, M_VALUE>;
+  extern __shared__ float lds[];
+
+  const Shape& sh = args.sh;
+  const int Wp = sh.Wp, NW = sh.NW, H = sh.H;
+  const int K4 = Wp / 16;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, w = tid >> 6, g = lane >> 4, j = lane & 15;
+  const StepLds L = step_lds(D, Wp, H, NCB);
+  float* bufH = lds + L.bufH;
+  float* bufG = lds + L.bufG;
+  float* ys = lds + L.ys;
+  float* yb = lds + L.yb;
+  float* xin = lds + L.xin;
+  float* acc1 = lds + L.acc1;
+  float* dbacc = lds + L.dbacc;
+  float* red = lds + L.red;
+  const int S = L.S, S2 = L.S2;
+
+  float* stash_w = args.stash + (size_t)blockIdx.x * args.stash_per_wg + (size_t)w * H * NCB * 256;
+  const float nu = args.nu;
+
+  // segment accumulators
+  float lacc[6];
+  float dwo = 0.f, dbo = 0.f;
+
+  const int it0 = args.wg_begin[blockIdx.x], it1 = args.wg_begin[blockIdx.x + 1];
+  for (int it = it0; it < it1; ++it) {
+    __syncthreads();   // the previous tile's readers of xin/acc1 are done
+    const Item item = args.items[it];
+    const SubDev& sd = args.subs[item.sub];
+    const float* fr = sd.frag;
+    const float* W1p = fr + sh.f_w1;
+    const float* bp = fr + sh.f_b;
+    const float* Wop = fr + sh.f_wo;
+    const float* bop = fr + sh.f_bo;
+    const bool pde = item.kind == ITEM_PDE;
+
+    if (item.flags & ITEM_FIRST) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) lacc[k] = 0.f;
+      dwo = 0.f;
+      dbo = 0.f;
+      for (int k = tid; k < Wp * D; k += nthr) acc1[k] = 0.f;
+      for (int k = tid; k < H * Wp; k += nthr) dbacc[k] = 0.f;
+    }
+
+    // ---- stage the tile's input points into LDS
+    if (pde) {
+      for (int k = tid; k < MP::NPTS * D; k += nthr) {
+        const int pt = k / D;
+        xin[k] = (pt < item.count) ? sd.pde_x[(size_t)(item.start + pt) * D + (k - pt * D)] : 0.f;
+      }
+    } else {
+      for (int k = tid; k < NCOL * D; k += nthr) {
+        const int pt = k / D, q = k - pt * D;
+        float v = 0.f;
+        if (pt < item.count) {
+          int idx = item.start + pt;
+          if (idx < sd.n_obs) v = sd.obs_x[(size_t)idx * D + q];
+          else if ((idx -= sd.n_obs) < sd.n_gh) v = sd.gh_x[(size_t)idx * D + q];
+          else v = sd.anc_x[(size_t)(idx - sd.n_gh) * D + q];
+        }
+        xin[k] = v;
+      }
+    }
+    __syncthreads();
+
+    v4f acc[NCB];
+    // ---- forward: input layer
+    if (pde) input_layer<DIM, NCB, M_PDE>(acc, W1p, bp, xin, w, g, j);
+    else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      reinterpret_cast<v4f*>(stash_w)[(0 * NCB + cb) * 64 + lane] = acc[cb];
+    if (pde) act_forward<DIM, NCB, M_PDE>(acc);
+    else act_forward<DIM, NCB, M_VALUE>(acc);
+    store_fwd<NCB>(bufH, S, acc, w, g, j);
+    __syncthreads();
+
+    // ---- forward: hidden layers 2..H
+    for (int l = 2; l <= H; ++l) {
+      const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+      gemm_rows<NCB>(Wf, bufH, S, K4, g, j, lane, acc);
+      if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, g);
+      else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        reinterpret_cast<v4f*>(stash_w)[((l - 1) * NCB + cb) * 64 + lane] = acc[cb];
+      __syncthreads();
+      if (pde) act_forward<DIM, NCB, M_PDE>(acc);
+      else act_forward<DIM, NCB, M_VALUE>(acc);
+      store_fwd<NCB>(bufH, S, acc, w, g, j);
+      __syncthreads();
+    }
+
+    // ---- output layer
+    if (pde) output_layer<DIM, NCB, M_PDE>(bufH, S, Wp, Wop, bop, ys, tid, nthr);
+    else output_layer<DIM, NCB, M_VALUE>(bufH, S, Wp, Wop, bop, ys, tid, nthr);
+    __syncthreads();
+
+    // ---- residuals, losses and output seeds ybar = dL/dy
+    if (pde) {
+      if (tid < MP::NPTS) {
+        const int pb = tid >> 4, jj = tid & 15;
+        auto col = [&](int c) { return (c * MP::NPB + pb) * 16 + jj; };
+        auto Y = [&](int c, int o) { return ys[o * NCOL + col(c)]; };
+        float r[D];
+        residuals<DIM>(Y, nu, r);
+        const bool valid = tid < item.count;
+        float sq = 0.f;
+        float rb[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+          if (!valid) r[k] = 0.f;
+          sq += r[k] * r[k];
+          rb[k] = 2.f * sd.lam[1] * sd.inv_n[0] * r[k];
+        }
+        lacc[1] += sq;
+        // dL/dy for every channel (derivative of sum_k rb_k r_k / 2 ...)
+#pragma unroll
+        for (int i = 0; i < DIM; ++i) {
+          float s = 0.f;
+#pragma unroll
+          for (int k = 0; k < DIM; ++k) s += rb[k] * Y(1 + i, k);
+          yb[i * NCOL + col(0)] = s;                              // u_i
+#pragma unroll
+          for (int jx = 0; jx < DIM; ++jx) {
+            yb[i * NCOL + col(1 + jx)] = rb[i] * Y(0, jx) + (i == jx ? rb[DIM] : 0.f);   // d_j u_i
+            yb[i * NCOL + col(DIM + 2 + jx)] = -nu * rb[i];                               // d_jj u_i
+          }
+          yb[i * NCOL + col(1 + DIM)] = rb[i];                     // d_t u_i
+        }
+        yb[DIM * NCOL + col(0)] = 0.f;                             // p
+#pragma unroll
+        for (int jx = 0; jx < DIM; ++jx) {
+          yb[DIM * NCOL + col(1 + jx)] = rb[jx];                   // d_j p
+          yb[DIM * NCOL + col(DIM + 2 + jx)] = 0.f;
+        }
+        yb[DIM * NCOL + col(1 + DIM)] = 0.f;
+      }
+    } else {
+      // one column per point; a workgroup may have fewer threads than columns
+      for (int col = tid; col < NCOL; col += nthr) {
+        float e[D];
+#pragma unroll
+        for (int o = 0; o < D; ++o) e[o] = 0.f;
+        if (col < item.count) {
+          int idx = item.start + col;
+          float y[D];
+#pragma unroll
+          for (int o = 0; o < D; ++o) y[o] = ys[o * NCOL + col];
+          if (idx < sd.n_obs) {
+            float sq = 0.f;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+              const float d0 = y[i] - sd.obs_u[(size_t)idx * DIM + i];
+              sq += d0 * d0;
+              e[i] = 2.f * sd.lam[0] * sd.inv_n[1] * d0;
+            }
+            lacc[0] += sq;
+          } else if ((idx -= sd.n_obs) < sd.n_gh) {
+            float sq = 0.f;
+            const float* tg = sd.gh_up + (size_t)idx * D;
+#pragma unroll
+            for (int i = 0; i < DIM; ++i) {
+              const float d0 = y[i] - tg[i];
+              sq += d0 * d0;
+              e[i] = 2.f * sd.lam[2] * sd.inv_n[2] * d0;
+            }
+            lacc[2] += sq;
+            const float dp = y[DIM] - tg[DIM];
+            if (sd.gh_kind[idx]) {
+              lacc[4] += dp * dp;
+              e[DIM] = 2.f * sd.lam[4] * sd.inv_n[2] * dp;
+            } else {
+              lacc[3] += dp * dp;
+              e[DIM] = 2.f * sd.lam[3] * sd.inv_n[2] * dp;
+            }
+          } else {
+            idx -= sd.n_gh;
+            const float dp = y[DIM] - sd.anc_p[idx];
+            lacc[5] += dp * dp;
+            e[DIM] = 2.f * sd.lam[5] * sd.inv_n[3] * dp;
+          }
+        }
+#pragma unroll
+        for (int o = 0; o < D; ++o) yb[o * NCOL + col] = e[o];
+      }
+    }
+    __syncthreads();
+
+    // ---- output layer adjoint
+    {
+      const int npb = pde ? MP::NPB : MV::NPB;
+      if (tid < D * Wp) {
+        const int o = tid / Wp, n = tid - o * Wp;
+        float s = 0.f;
+        for (int col = 0; col < NCOL; ++col) s += yb[o * NCOL + col] * bufH[col * S + n];
+        dwo += s;
+      }
+      if (tid < D) {
+        float s = 0.f;
+        for (int col = 0; col < 16 * npb; ++col) s += yb[tid * NCOL + col];
+        dbo += s;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * w + 4 * g + i;
+        float wo[D];
+#pragma unroll
+        for (int o = 0; o < D; ++o) wo[o] = Wop[o * Wp + r];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          float s = 0.f;
+#pragma unroll
+          for (int o = 0; o < D; ++o) s += wo[o] * yb[o * NCOL + 16 * cb + j];
+          acc[cb][i] = s;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- hidden and input layer adjoints
+    v4f zs[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      zs[cb] = reinterpret_cast<const v4f*>(stash_w)[((H - 1) * NCB + cb) * 64 + lane];
+    for (int l = H; l >= 1; --l) {
+      if (pde) act_adjoint<DIM, NCB, M_PDE>(acc, zs);
+      else act_adjoint<DIM, NCB, M_VALUE>(acc, zs);
+      // db_l: value-channel columns
+      {
+        const int npb = pde ? MP::NPB : MV::NPB;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float s = 0.f;
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            if (cb < npb) s += acc[cb][i];
+          s = sum16(s);
+          if (j == 0) dbacc[(l - 1) * Wp + 16 * w + 4 * g + i] += s;
+        }
+      }
+      if (l == 1) {
+        // input layer: dW1[r][q] += sum_pts zbar0 xi_q + zbar_q (first-derivative channel q)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int r = 16 * w + 4 * g + i;
+          float v[D];
+#pragma unroll
+          for (int q = 0; q < D; ++q) v[q] = 0.f;
+          if (pde) {
+#pragma unroll
+            for (int pb = 0; pb < MP::NPB; ++pb) {
+              const float* xp = xin + (16 * pb + j) * D;
+#pragma unroll
+              for (int q = 0; q < D; ++q)
+                v[q] += acc[pb][i] * xp[q] + acc[(1 + q) * MP::NPB + pb][i];
+            }
+          } else {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+              const float* xp = xin + (16 * cb + j) * D;
+#pragma unroll
+              for (int q = 0; q < D; ++q) v[q] += acc[cb][i] * xp[q];
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < D; ++q) {
+            const float s = sum16(v[q]);
+            if (j == 0) acc1[r * D + q] += s;
+          }
+        }
+        break;
+      }
+      store_fwd<NCB>(bufG, S, acc, w, g, j);
+      // recompute h_{l-1} from the stashed z_{l-1}; keep z_{l-1} for the next adjoint
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        zs[cb] = reinterpret_cast<const v4f*>(stash_w)[((l - 2) * NCB + cb) * 64 + lane];
+      {
+        v4f hv[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) hv[cb] = zs[cb];
+        if (pde) act_forward<DIM, NCB, M_PDE>(hv);
+        else act_forward<DIM, NCB, M_VALUE>(hv);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) bufH[(16 * w + 4 * g + i) * S2 + 16 * cb + j] = hv[cb][i];
+      }
+      __syncthreads();
+      // dW_l += Zbar_l H_{l-1}^T into this segment's slab
+      {
+        float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
+        v4f* swv = reinterpret_cast<v4f*>(sw);
+        for (int nb0 = 0; nb0 < NW; nb0 += 4) {
+          const int nnb = (NW - nb0) < 4 ? (NW - nb0) : 4;
+          v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
+          gemm_dw<NCB>(bufG, S, bufH, S2, w, g, j, nb0, nnb, dw);
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            if (t < nnb) {
+              v4f* p = swv + (size_t)(w * NW + nb0 + t) * 64 + lane;
+              if (item.flags & ITEM_FIRST) *p = dw[t];
+              else *p = *p + dw[t];
+            }
+          }
+        }
+      }
+      // Hbar_{l-1} = W_l^T Zbar_l
+      {
+        const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+        gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc);
+      }
+      __syncthreads();
+    }
+
+    // ---- end of segment: write the accumulated gradient pieces and losses
+    if (item.flags & ITEM_LAST) {
+      __syncthreads();
+      float* slab = args.slabs + (size_t)item.slab * sh.slab_floats;
+      for (int k = tid; k < Wp * D; k += nthr) slab[sh.s_w1 + k] = acc1[k];
+      for (int k = tid; k < H * Wp; k += nthr) slab[sh.s_b + k] = dbacc[k];
+      if (tid < D * Wp) slab[sh.s_wo + tid] = dwo;
+      if (tid < 4) slab[sh.s_bo + tid] = (tid < D) ? dbo : 0.f;
+      // loss partials: wave sums, then across waves
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        float v = lacc[k];
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        if (lane == 0) red[w * 8 + k] = v;
+      }
+      __syncthreads();
+      if (tid < 8) {
+        float v = 0.f;
+        if (tid < 6)
+          for (int q = 0; q < NW; ++q) v += red[q * 8 + tid];
+        slab[sh.s_loss + tid] = v;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// prep: fragment-ordered copies of the weights (zero padded to Wp)
+// ---------------------------------------------------------------------------
+__global__ void prep_kernel(const PrepArgs a) {
+  const Shape& sh = a.sh;
+  const int s = blockIdx.y;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= sh.frag_floats) return;
+  const float* th = a.subs[s].theta;
+  float* fr = a.subs[s].frag;
+  const int W = sh.W, Wp = sh.Wp, D = sh.D, H = sh.H;
+  float v = 0.f;
+  if (idx < sh.f_w1) {
+    const int64_t per = 2LL * Wp * Wp;
+    const int l = 2 + (int)(idx / per);
+    const int64_t rem = idx - (int64_t)(l - 2) * per;
+    const bool trans = rem >= (int64_t)Wp * Wp;
+    const int e = (int)(trans ? rem - (int64_t)Wp * Wp : rem);
+    const int q = e & 3, lane = (e >> 2) & 63, t = e >> 8;
+    const int K4 = Wp / 16;
+    const int s4 = t % K4, w = t / K4;
+    const int k = (lane >> 4) * (Wp / 4) + 4 * s4 + q;
+    const int r = 16 * w + (lane & 15);
+    if (r < W && k < W) v = trans ? th[sh.p_w[l] + (int64_t)k * W + r] : th[sh.p_w[l] + (int64_t)r * W + k];
+  } else if (idx < sh.f_b) {
+    const int e = (int)(idx - sh.f_w1), r = e / D, q = e - r * D;
+    if (r < W) v = th[sh.p_w[1] + (int64_t)r * D + q];
+  } else if (idx < sh.f_wo) {
+    const int e = (int)(idx - sh.f_b), l = 1 + e / Wp, r = e % Wp;
+    if (r < W) v = th[sh.p_b[l] + r];
+  } else if (idx < sh.f_bo) {
+    const int e = (int)(idx - sh.f_wo), o = e / Wp, n = e % Wp;
+    if (n < W) v = th[sh.p_w[H + 1] + (int64_t)o * W + n];
+  } else if (idx < sh.f_bo + 4) {
+    const int o = (int)(idx - sh.f_bo);
+    if (o < D) v = th[sh.p_b[H + 1] + o];
+  }
+  fr[idx] = v;
+}
+
+// ---------------------------------------------------------------------------
+// reduce + Adam: sum this subdomain's slabs in a fixed order; Adam in place
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t slab_pos(const Shape& sh, int64_t p) {
+  const int W = sh.W, Wp = sh.Wp, D = sh.D, H = sh.H;
+  if (p < sh.p_b[1]) {                        // W1 [W][D]
+    const int64_t r = p / D, q = p - r * D;
+    return sh.s_w1 + r * D + q;
+  }
+  if (p < sh.p_w[2 <= H ? 2 : H + 1]) {       // b1
+    return sh.s_b + (p - sh.p_b[1]);
+  }
+  for (int l = 2; l <= H; ++l) {
+    if (p < sh.p_b[l]) {                      // W_l [W][W] in accumulator order
+      const int64_t e = p - sh.p_w[l];
+      const int r = (int)(e / W), c = (int)(e - (int64_t)r * W);
+      const int w = r >> 4, g = (r & 15) >> 2, i = r & 3, nb = c >> 4, jj = c & 15;
+      return sh.s_hid + (int64_t)(l - 2) * Wp * Wp + ((int64_t)(w * sh.NW + nb) * 64 + g * 16 + jj) * 4 + i;
+    }
+    if (p < sh.p_w[l + 1]) return sh.s_b + (int64_t)(l - 1) * Wp + (p - sh.p_b[l]);
+  }
+  if (p < sh.p_b[H + 1]) {                    // W_{H+1} [D][W]
+    const int64_t e = p - sh.p_w[H + 1];
+    const int o = (int)(e / W), n = (int)(e - (int64_t)o * W);
+    return sh.s_wo + (int64_t)o * Wp + n;
+  }
+  return sh.s_bo + (p - sh.p_b[H + 1]);
+}
+
+__global__ void reduce_kernel(const ReduceArgs a) {
+  const Shape& sh = a.sh;
+  const int s = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k0 = a.seg_begin[s], k1 = a.seg_begin[s + 1];
+  const SubDev& sd = a.subs[s];
+  if (p < sh.P) {
+    const int64_t pos = slab_pos(sh, p);
+    float g = 0.f;
+    for (int k = k0; k < k1; ++k) g += a.slabs[(size_t)k * sh.slab_floats + pos];
+    if (a.grad_out) a.grad_out[(size_t)s * sh.P + p] = g;
+    if (a.update) {
+      const float m = a.beta1 * sd.m[p] + (1.f - a.beta1) * g;
+      const float v = a.beta2 * sd.v[p] + (1.f - a.beta2) * g * g;
+      sd.m[p] = m;
+      sd.v[p] = v;
+      const float c1 = 1.f - powf(a.beta1, (float)a.t);
+      const float c2 = 1.f - powf(a.beta2, (float)a.t);
+      float* th = const_cast<float*>(sd.theta);
+      th[p] = th[p] - a.lr * (m / c1) / (sqrtf(v / c2) + a.eps);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    float L[7];
+    for (int q = 0; q < 6; ++q) {
+      float v = 0.f;
+      for (int k = k0; k < k1; ++k) v += a.slabs[(size_t)k * sh.slab_floats + sh.s_loss + q];
+      L[q] = v;
+    }
+    L[0] *= sd.inv_n[1];
+    L[1] *= sd.inv_n[0];
+    L[2] *= sd.inv_n[2];
+    L[3] *= sd.inv_n[2];
+    L[4] *= sd.inv_n[2];
+    L[5] *= sd.inv_n[3];
+    L[6] = sd.lam[0] * L[0] + sd.lam[1] * L[1] + sd.lam[2] * L[2] + sd.lam[3] * L[3] +
+           sd.lam[4] * L[4] + sd.lam[5] * L[5];
+    for (int q = 0; q < 7; ++q) {
+      a.loss_ws[s * 8 + q] = L[q];
+      if (a.loss_out) a.loss_out[s * 7 + q] = L[q];
+    }
+    a.loss_ws[s * 8 + 7] = 0.f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// query: routing (bin points by subdomain box) and grouped forward
+// ---------------------------------------------------------------------------
+__global__ void route_zero_kernel(int32_t* counts, int32_t* cursor, int n_sub) {
+  for (int s = threadIdx.x; s < n_sub; s += blockDim.x) { counts[s] = 0; cursor[s] = 0; }
+}
+
+__global__ void route_count_kernel(const RouteArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float* x = a.x + i * a.D;
+  int found = -1;
+  for (int s = 0; s < a.n_sub && found < 0; ++s) {
+    const float* lo = a.boxes + s * 8;
+    const float* hi = lo + 4;
+    bool in = true;
+    for (int q = 0; q < a.D; ++q) {
+      const float c = x[q];
+      const bool ok = (c >= lo[q]) && (c < hi[q] || (c == hi[q] && hi[q] == a.gmax[q]));
+      if (!ok) { in = false; break; }
+    }
+    if (in) found = s;
+  }
+  a.sub_id[i] = found;
+  if (found >= 0) atomicAdd(a.counts + found, 1);
+  else
+    for (int q = 0; q < a.out_cols; ++q) a.out[i * a.out_cols + q] = __builtin_nanf("");
+}
+
+__global__ void route_offsets_kernel(const RouteArgs a) {
+  if (threadIdx.x == 0) {
+    int32_t acc = 0;
+    for (int s = 0; s < a.n_sub; ++s) { a.offsets[s] = acc; acc += a.counts[s]; }
+    a.offsets[a.n_sub] = acc;
+  }
+}
+
+__global__ void route_scatter_kernel(const RouteArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int s = a.sub_id[i];
+  if (s < 0) return;
+  const int slot = a.offsets[s] + atomicAdd(a.cursor + s, 1);
+  a.perm[slot] = (int32_t)i;
+}
+
+struct QueryLds { int S, NCOL, bufH, ys, xin, pidx, total; };
+__host__ __device__ inline QueryLds query_lds(int D, int Wp, int NCB) {
+  QueryLds L;
+  L.NCOL = 16 * NCB;
+  L.S = Wp + 4;
+  int o = 0;
+  L.bufH = o; o += (L.NCOL * L.S + 3) & ~3;
+  L.ys = o;   o += (D * L.NCOL + 3) & ~3;
+  L.xin = o;  o += (L.NCOL * D + 3) & ~3;
+  L.pidx = o; o += L.NCOL;
+  L.total = o;
+  return L;
+}
+
+// forward of one staged tile (points in xin) through all layers; output in ys
+template <int DIM, int NCB, int MODE>
+__device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, float* bufH, float* ys,
+                                             const float* xin, int S, int tid, int nthr, int w, int g,
+                                             int j, int lane) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  const int Wp = sh.Wp, H = sh.H, K4 = Wp / 16;
+  v4f acc[NCB];
+  input_layer<DIM, NCB, MODE>(acc, fr + sh.f_w1, fr + sh.f_b, xin, w, g, j);
+  act_forward<DIM, NCB, MODE>(acc);
+  store_fwd<NCB>(bufH, S, acc, w, g, j);
+  __syncthreads();
+  for (int l = 2; l <= H; ++l) {
+    const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+    gemm_rows<NCB>(Wf, bufH, S, K4, g, j, lane, acc);
+    add_bias<NCB, M::NPB>(acc, fr + sh.f_b + (l - 1) * Wp, w, g);
+    __syncthreads();
+    act_forward<DIM, NCB, MODE>(acc);
+    store_fwd<NCB>(bufH, S, acc, w, g, j);
+    __syncthreads();
+  }
+  output_layer<DIM, NCB, MODE>(bufH, S, Wp, fr + sh.f_wo, fr + sh.f_bo, ys, tid, nthr);
+  __syncthreads();
+}
+
+template <int DIM, int MODE>
+__global__ __launch_bounds__(512) void query_kernel(const QueryArgs a) {
+  constexpr int D = DIM + 1, CF = 2 * DIM + 2, NCB = CF;
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int NPTS = M::NPTS, NCOL = 16 * NCB;
+  extern __shared__ float lds[];
+  const Shape& sh = a.sh;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, w = tid >> 6, g = lane >> 4, j = lane & 15;
+  const QueryLds L = query_lds(D, sh.Wp, NCB);
+  float* bufH = lds + L.bufH;
+  float* ys = lds + L.ys;
+  float* xin = lds + L.xin;
+  int32_t* pidx = reinterpret_cast<int32_t*>(lds + L.pidx);
+
+  // tiles: for routed queries, subdomain s holds points [offsets[s], offsets[s]+counts[s])
+  const int nsub = a.counts ? a.n_sub : 1;
+  int64_t total = 0;
+  for (int s = 0; s < nsub; ++s) {
+    const int64_t c = a.counts ? a.counts[s] : a.n;
+    total += (c + NPTS - 1) / NPTS;
+  }
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int s = 0;
+    int64_t tl = t, c = 0;
+    for (; s < nsub; ++s) {
+      c = a.counts ? a.counts[s] : a.n;
+      const int64_t nt = (c + NPTS - 1) / NPTS;
+      if (tl < nt) break;
+      tl -= nt;
+    }
+    const int sub = a.counts ? s : a.sub;
+    const int64_t base = (a.counts ? a.offsets[s] : 0) + tl * NPTS;
+    const int cnt = (int)((c - tl * NPTS) < NPTS ? (c - tl * NPTS) : NPTS);
+    for (int k = tid; k < NPTS; k += nthr)
+      pidx[k] = (k < cnt) ? (a.perm ? a.perm[base + k] : (int32_t)(base + k)) : -1;
+    __syncthreads();
+    for (int k = tid; k < NCOL * D; k += nthr) {
+      const int pt = k / D;
+      float v = 0.f;
+      if (pt < NPTS && pidx[pt] >= 0) v = a.x[(size_t)pidx[pt] * D + (k - pt * D)];
+      xin[k] = v;
+    }
+    __syncthreads();
+    forward_tile<DIM, NCB, MODE>(sh, a.subs[sub].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
+    for (int k = tid; k < NPTS; k += nthr) {
+      if (pidx[k] < 0) continue;
+      const int64_t q = pidx[k];
+      const int pb = k >> 4, jj = k & 15;
+      auto Y = [&](int ch, int o) { return ys[o * NCOL + (ch * M::NPB + pb) * 16 + jj]; };
+      if (a.what == Q_VALUE) {
+        for (int o = 0; o < D; ++o) a.out[q * D + o] = Y(0, o);
+      } else if (a.what == Q_UVPW) {
+        if constexpr (MODE == M_GRAD && DIM == 2) {
+          a.out[q * 4 + 0] = Y(0, 0);
+          a.out[q * 4 + 1] = Y(0, 1);
+          a.out[q * 4 + 2] = Y(0, 2);
+          a.out[q * 4 + 3] = Y(1, 1) - Y(2, 0);   // v_x - u_y
+        }
+      } else if (a.what == Q_CHANNELS) {
+        if constexpr (MODE == M_PDE)
+          for (int ch = 0; ch < CF; ++ch)
+            for (int o = 0; o < D; ++o) a.out[(q * CF + ch) * D + o] = Y(ch, o);
+      } else {
+        if constexpr (MODE == M_PDE) {
+          float r[D];
+          residuals<DIM>(Y, a.nu, r);
+          for (int k = 0; k < D; ++k) a.out[q * D + k] = r[k];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// exchange: neighbour values at ghost points, anchor-normalised pressure
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(512) void exchange_kernel(const ExchangeArgs a) {
+  constexpr int D = DIM + 1, CF = 2 * DIM + 2, NCB = CF, NCOL = 16 * NCB;
+  extern __shared__ float lds[];
+  const Shape& sh = a.sh;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, w = tid >> 6, g = lane >> 4, j = lane & 15;
+  const QueryLds L = query_lds(D, sh.Wp, NCB);
+  float* bufH = lds + L.bufH;
+  float* ys = lds + L.ys;
+  float* xin = lds + L.xin;
+  for (int t = blockIdx.x; t < a.n_items; t += gridDim.x) {
+    const ExchangeItem it = a.items[t];
+    const SubDev& ra = a.subs[it.a];
+    const int half = NCOL / 2;
+    for (int k = tid; k < NCOL * D; k += nthr) {
+      const int pt = k / D, q = k - pt * D;
+      float v = 0.f;
+      if (it.paired) {
+        const int pp = pt < half ? pt : pt - half;
+        if (pp < it.count) {
+          const float* gx = ra.gh_x + (size_t)(it.start + pp) * D;
+          v = (pt < half) ? gx[q] : (q < DIM ? a.x_anc[q] : gx[DIM]);
+        }
+      } else if (pt < it.count) {
+        v = ra.gh_x[(size_t)(it.start + pt) * D + q];
+      }
+      xin[k] = v;
+    }
+    __syncthreads();
+    forward_tile<DIM, NCB, M_VALUE>(sh, a.subs[it.b].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
+    float* tg = a.targets[it.a];
+    for (int k = tid; k < it.count; k += nthr) {
+      for (int o = 0; o < D; ++o) {
+        float v = ys[o * NCOL + k];
+        if (o == DIM && it.paired) v -= ys[o * NCOL + half + k];
+        tg[(size_t)(it.start + k) * D + o] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void nonfinite_kernel(const float* loss_ws, int n_sub, int32_t* flag) {
+  int bad = 0;
+  for (int k = threadIdx.x; k < n_sub * 8; k += blockDim.x)
+    if (!isfinite(loss_ws[k])) bad = 1;
+  if (bad) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int step_value_points(int dim, int tile_points) {
+  return 16 * (2 * dim + 2) * (tile_points / 16);
+}
+
+int step_lds_floats(const Shape& sh, int tile_points) {
+  const int NCB = (2 * sh.dim + 2) * (tile_points / 16);
+  return step_lds(sh.D, sh.Wp, sh.H, NCB).total;
+}
+
+int query_lds_floats(const Shape& sh) {
+  return query_lds(sh.D, sh.Wp, 2 * sh.dim + 2).total;
+}
+
+const void* step_kernel_ptr(int dim, int tile_points) {
+  if (dim == 2) return tile_points == 32 ? (const void*)step_kernel<2, 2> : (const void*)step_kernel<2, 1>;
+  return tile_points == 32 ? (const void*)step_kernel<3, 2> : (const void*)step_kernel<3, 1>;
+}
+const void* prep_kernel_ptr() { return (const void*)prep_kernel; }
+const void* reduce_kernel_ptr() { return (const void*)reduce_kernel; }
+
+void grid_prep(const PrepArgs& a, dim3* grid, dim3* block) {
+  *block = dim3(256);
+  *grid = dim3((unsigned)((a.sh.frag_floats + 255) / 256), (unsigned)a.n_sub);
+}
+void grid_reduce(const ReduceArgs& a, dim3* grid, dim3* block) {
+  *block = dim3(256);
+  *grid = dim3((unsigned)((a.sh.P + 255) / 256), (unsigned)a.n_sub);
+}
+
+hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
+  dim3 grid, block;
+  grid_prep(a, &grid, &block);
+  hipLaunchKernelGGL(prep_kernel, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(const StepArgs& a, int tile_points, int n_wg, hipStream_t s) {
+  const size_t lds = (size_t)a.lds_floats * sizeof(float);
+  const dim3 block(a.sh.NW * 64);
+  if (a.sh.dim == 2) {
+    if (tile_points == 32) hipLaunchKernelGGL((step_kernel<2, 2>), dim3(n_wg), block, lds, s, a);
+    else hipLaunchKernelGGL((step_kernel<2, 1>), dim3(n_wg), block, lds, s, a);
+  } else {
+    if (tile_points == 32) hipLaunchKernelGGL((step_kernel<3, 2>), dim3(n_wg), block, lds, s, a);
+    else hipLaunchKernelGGL((step_kernel<3, 1>), dim3(n_wg), block, lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  dim3 grid, block;
+  grid_reduce(a, &grid, &block);
+  hipLaunchKernelGGL(reduce_kernel, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(route_zero_kernel, dim3(1), dim3(256), 0, s, a.counts, a.cursor, a.n_sub);
+  const unsigned nb = (unsigned)((a.n + 255) / 256);
+  if (nb) hipLaunchKernelGGL(route_count_kernel, dim3(nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(route_offsets_kernel, dim3(1), dim3(64), 0, s, a);
+  if (nb) hipLaunchKernelGGL(route_scatter_kernel, dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_query(const QueryArgs& a, int n_wg, hipStream_t s) {
+  const size_t lds = (size_t)a.lds_floats * sizeof(float);
+  const dim3 block(a.sh.NW * 64);
+  const int mode = (a.what == Q_VALUE) ? M_VALUE : (a.what == Q_UVPW ? M_GRAD : M_PDE);
+  if (a.sh.dim == 2) {
+    if (mode == M_VALUE) hipLaunchKernelGGL((query_kernel<2, M_VALUE>), dim3(n_wg), block, lds, s, a);
+    else if (mode == M_GRAD) hipLaunchKernelGGL((query_kernel<2, M_GRAD>), dim3(n_wg), block, lds, s, a);
+    else hipLaunchKernelGGL((query_kernel<2, M_PDE>), dim3(n_wg), block, lds, s, a);
+  } else {
+    if (mode == M_VALUE) hipLaunchKernelGGL((query_kernel<3, M_VALUE>), dim3(n_wg), block, lds, s, a);
+    else if (mode == M_GRAD) hipLaunchKernelGGL((query_kernel<3, M_GRAD>), dim3(n_wg), block, lds, s, a);
+    else hipLaunchKernelGGL((query_kernel<3, M_PDE>), dim3(n_wg), block, lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_exchange(const ExchangeArgs& a, int n_wg, hipStream_t s) {
+  const size_t lds = (size_t)a.lds_floats * sizeof(float);
+  const dim3 block(a.sh.NW * 64);
+  if (a.sh.dim == 2) hipLaunchKernelGGL((exchange_kernel<2>), dim3(n_wg), block, lds, s, a);
+  else hipLaunchKernelGGL((exchange_kernel<3>), dim3(n_wg), block, lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_nonfinite_check(const float* loss_ws, int n_sub, int32_t* flag, hipStream_t s) {
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(1), dim3(256), 0, s, loss_ws, n_sub, flag);
+  return hipGetLastError();
+}
+
+// LDS above 64 KiB must be allowed per kernel before launch.
+hipError_t set_lds_limits(int bytes) {
+  hipError_t e = hipSuccess;
+  const void* ks[] = {(const void*)step_kernel<2, 1>, (const void*)step_kernel<2, 2>,
+                      (const void*)step_kernel<3, 1>, (const void*)step_kernel<3, 2>,
+                      (const void*)query_kernel<2, M_VALUE>, (const void*)query_kernel<2, M_GRAD>,
+                      (const void*)query_kernel<2, M_PDE>, (const void*)query_kernel<3, M_VALUE>,
+                      (const void*)query_kernel<3, M_GRAD>, (const void*)query_kernel<3, M_PDE>,
+                      (const void*)exchange_kernel<2>, (const void*)exchange_kernel<3>};
+  for (const void* k : ks) {
+    hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (r != hipSuccess) e = r;
+  }
+  return e;
+}
+
+}  // namespace ddp

@@ -1,0 +1,240 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Every case uses seeded synthetic inputs from workloads; the oracle sees the
+same float32 inputs converted exactly to float64.  Tolerances (tests/parity.py):
+values 1e-5, first derivatives 1e-4, second derivatives and residuals 1e-3,
+gradients 1e-3 (relative, with an rms floor).
+"""
+import numpy as np
+import pytest
+
+import workloads as wl
+from parity import (TOL_GRAD, TOL_LOSS, TOL_RESIDUAL, assert_close, channel_tolerances,
+                    oracle_loss_grad)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_15883_amd as P
+    P.lib()
+    return P
+
+
+def ctx_of(P, pb, **kw):
+    return P.context_from_problem(pb, device="cuda", **kw)
+
+
+def gpu_loss_grad(ctx):
+    loss, g = ctx.step(1, update=False, want_grad=True)
+    torch.cuda.synchronize()
+    return loss.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+
+
+def check_channels(P, ctx, orc, pb, x, sub=0, label=""):
+    dim = pb.dim
+    D = dim + 1
+    xt = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+    ch = ctx.query(xt, sub=sub, what="channels").cpu().numpy().reshape(len(x), 2 * dim + 2, D)
+    ref = orc.channels(dim, pb.width, pb.depth, pb.subs[sub].theta, x)
+    for c, tol in enumerate(channel_tolerances(dim)):
+        assert_close(ch[:, c, :], ref[:, c, :], tol, f"{label} channel {c}")
+    r = ctx.query(xt, sub=sub, what="residual").cpu().numpy()
+    rref = orc.residuals(dim, pb.nu, ref)
+    assert_close(r, rref, TOL_RESIDUAL, f"{label} residuals")
+
+
+TINY = [(2, 5, 2, 7, 5, 4, 2), (3, 5, 3, 19, 9, 6, 1), (2, 20, 1, 33, 0, 0, 0),
+        (2, 16, 2, 16, 3, 0, 2), (3, 33, 2, 40, 100, 130, 3), (2, 50, 3, 1, 1, 1, 1)]
+
+
+@pytest.mark.parametrize("dim,W,H,npde,nobs,ngh,nanc", TINY)
+def test_tiny_loss_grad_channels(pkg, orc, dim, W, H, npde, nobs, ngh, nanc):
+    pb = wl.tiny(dim=dim, width=W, depth=H, n_pde=npde, n_obs=nobs, n_gh=ngh, n_anc=nanc, seed=W + H)
+    ctx = ctx_of(pkg, pb, graph=False)
+    L, g = gpu_loss_grad(ctx)
+    Lr, gr = oracle_loss_grad(orc, pb)
+    assert_close(L[0], Lr, TOL_LOSS, "loss")
+    assert_close(g[0], gr, TOL_GRAD, "grad")
+    check_channels(pkg, ctx, orc, pb, pb.subs[0].pde_x, label="tiny")
+    ctx.close()
+
+
+def test_config1_full_step(pkg, orc):
+    pb = wl.config1(0)
+    s = pb.subs[0]
+    ctx = ctx_of(pkg, pb, graph=True)
+    check_channels(pkg, ctx, orc, pb, s.pde_x, label="config1")
+    L, g = gpu_loss_grad(ctx)
+    Lr, gr = oracle_loss_grad(orc, pb)
+    assert_close(L[0], Lr, TOL_LOSS, "loss")
+    assert_close(g[0], gr, TOL_GRAD, "grad")
+    # one Adam step (t = 1) from zero moments
+    th0 = ctx.subs[0].theta.cpu().numpy().astype(np.float64)
+    ctx.step(1, update=True)
+    torch.cuda.synchronize()
+    th1 = ctx.subs[0].theta.cpu().numpy().astype(np.float64)
+    m1 = ctx.subs[0].adam_m.cpu().numpy().astype(np.float64)
+    # (1) the Adam update applied to the GPU's own gradient
+    t_own, m_own, _ = orc.adam(th0, np.zeros_like(th0), np.zeros_like(th0), g[0], 1, lr=pb.lr)
+    assert_close(th1, t_own, 1e-6, "adam on own gradient")
+    assert_close(m1, m_own, 1e-6, "adam first moment")
+    # (2) against the oracle's gradient, excluding sign-ambiguous entries
+    t_ref, _, _ = orc.adam(th0, np.zeros_like(th0), np.zeros_like(th0), gr, 1, lr=pb.lr)
+    amb = np.abs(gr) <= TOL_GRAD * (np.abs(gr) + np.sqrt(np.mean(gr * gr)))
+    assert amb.mean() < 0.05
+    assert_close(th1[~amb], t_ref[~amb], 1e-6, "theta after Adam")
+    ctx.close()
+
+
+@pytest.mark.parametrize("n_pde", [3000, 2999])
+def test_config2_reduced(pkg, orc, n_pde):
+    pb = wl.config2(0, n_pde=n_pde)
+    s = pb.subs[0]
+    s.obs_x, s.obs_u = s.obs_x[:700], s.obs_u[:700]
+    s.gh_x, s.gh_up, s.gh_kind = s.gh_x[:333], s.gh_up[:333], s.gh_kind[:333]
+    ctx = ctx_of(pkg, pb, graph=True)
+    L, g = gpu_loss_grad(ctx)
+    Lr, gr = oracle_loss_grad(orc, pb)
+    assert_close(L[0], Lr, TOL_LOSS, "loss")
+    assert_close(g[0], gr, TOL_GRAD, "grad")
+    check_channels(pkg, ctx, orc, pb, s.pde_x[:200], label="config2")
+    ctx.close()
+
+
+def test_config4_reduced(pkg, orc):
+    pb = wl.config4(0, n_pde=500, n_obs=90, n_gh_face=40)
+    ctx = ctx_of(pkg, pb, graph=True)
+    L, g = gpu_loss_grad(ctx)
+    Lr, gr = oracle_loss_grad(orc, pb)
+    assert_close(L[0], Lr, TOL_LOSS, "loss")
+    assert_close(g[0], gr, TOL_GRAD, "grad")
+    check_channels(pkg, ctx, orc, pb, pb.subs[0].pde_x[:64], label="config4")
+    ctx.close()
+
+
+def test_config4_full_size_sampled_channels(pkg, orc):
+    """Full 250k-point problem in the benchmark's launch configuration: the
+    channel stacks of sampled points match the oracle point by point."""
+    pb = wl.config4(0)
+    ctx = ctx_of(pkg, pb, graph=True)
+    loss, _ = ctx.step(1, update=False)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(loss.cpu().numpy()))
+    rng = np.random.default_rng(0)
+    idx = rng.choice(pb.subs[0].pde_x.shape[0], 48, replace=False)
+    check_channels(pkg, ctx, orc, pb, pb.subs[0].pde_x[idx], label="config4 full")
+    ctx.close()
+
+
+def test_config3_grouped_equals_per_subdomain_and_oracle(pkg, orc):
+    pb = wl.config3(0, pde_range=(300, 1300), n_obs=90, n_gh_face=37)
+    ctx = ctx_of(pkg, pb, graph=True)
+    L, g = gpu_loss_grad(ctx)
+    loss2, g2 = ctx.step(1, update=False, want_grad=True, per_subdomain=True)
+    torch.cuda.synchronize()
+    L2, g2 = loss2.cpu().numpy(), g2.cpu().numpy()
+    for s in range(len(pb.subs)):
+        Lr, gr = oracle_loss_grad(orc, pb, sub=s)
+        assert_close(L[s], Lr, TOL_LOSS, f"loss sub {s}")
+        assert_close(g[s], gr, TOL_GRAD, f"grad sub {s}")
+        assert_close(g2[s], gr, TOL_GRAD, f"per-sub grad sub {s}")
+        assert_close(L2[s], Lr, TOL_LOSS, f"per-sub loss sub {s}")
+    ctx.close()
+
+
+def test_graph_replay_equals_eager_and_is_deterministic(pkg):
+    pb = wl.config1(1)
+    outs = []
+    for graph in (True, False):
+        ctx = ctx_of(pkg, pb, graph=graph)
+        for t in range(1, 4):
+            loss, _ = ctx.step(t)
+            # eager work between replays
+            torch.cuda.synchronize()
+            _ = (ctx.subs[0].theta * 2).sum().item()
+        outs.append((loss.cpu().numpy().copy(), ctx.subs[0].theta.cpu().numpy().copy()))
+        ctx.close()
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+
+
+def test_query_routing_and_alone_vs_mix(pkg, orc):
+    boxes, thetas = wl.serving_nets(seed=3, width=20, depth=3)
+    subs = []
+    for s in range(len(thetas)):
+        sub = wl._sub(2, boxes[s][0], boxes[s][1], thetas[s])
+        subs.append(sub)
+    pb = wl.Problem("serve", 2, 20, 3, 0.01, np.ones(6), 1e-3, subs)
+    ctx = ctx_of(pkg, pb, graph=False)
+    rng = np.random.default_rng(1)
+    x = wl.query_points(rng, 3001)
+    x[:3] = [[0, 0, 0], [8, 2, 4], [9, 1, 1]]     # corner, global upper corner, outside
+    xt = torch.from_numpy(x).cuda()
+    out = ctx.query(xt, sub=-1, what="uvpw").cpu().numpy()
+    ref = orc.query2d(20, 3, thetas, boxes, x)
+    assert np.all(np.isnan(out[2])) and np.all(np.isnan(ref[2]))
+    ok = ~np.isnan(ref[:, 0])
+    assert_close(out[ok, :3], ref[ok, :3], 1e-5, "query uvp")
+    assert_close(out[ok, 3], ref[ok, 3], 1e-4, "query vorticity")
+    # each point's result is the same alone, in a small mix and in the full batch
+    for lo, hi in [(5, 6), (100, 117), (0, 3001)]:
+        part = ctx.query(xt[lo:hi].contiguous(), sub=-1, what="uvpw").cpu().numpy()
+        np.testing.assert_array_equal(part, out[lo:hi])
+    ctx.close()
+
+
+def test_exchange_matches_oracle(pkg, orc):
+    pb = wl.config3(0, pde_range=(100, 200), n_obs=10, n_gh_face=50)
+    ctx = ctx_of(pkg, pb, graph=False)
+    faces, targets = [], []
+    for a, s in enumerate(pb.subs):
+        for (b, kind, first, count) in s.faces:
+            faces.append((a, b, first, count))
+        targets.append(torch.zeros(s.gh_x.shape[0], 3, dtype=torch.float32, device="cuda"))
+    ctx.exchange(faces, pb.x_anc, targets)
+    torch.cuda.synchronize()
+    for (a, b, first, count) in faces:
+        x = pb.subs[a].gh_x[first:first + count]
+        ref = orc.exchange(2, pb.width, pb.depth, pb.subs[b].theta, pb.subs[b].is_master,
+                           pb.x_anc, x)
+        got = targets[a][first:first + count].cpu().numpy()
+        assert_close(got[:, :2], ref[:, :2], 1e-5, f"exchange u {a}<-{b}")
+        assert_close(got[:, 2], ref[:, 2], 1e-4, f"exchange p {a}<-{b}")
+    ctx.close()
+
+
+def test_empty_sets_and_single_points(pkg, orc):
+    pb = wl.tiny(dim=3, width=7, depth=2, n_pde=1, n_obs=0, n_gh=0, n_anc=0)
+    ctx = ctx_of(pkg, pb, graph=False)
+    L, g = gpu_loss_grad(ctx)
+    Lr, gr = oracle_loss_grad(orc, pb)
+    assert np.all(L[0, [0, 2, 3, 4, 5]] == 0)
+    assert_close(g[0], gr, TOL_GRAD, "grad")
+    ctx.close()
+    pb = wl.tiny(dim=2, width=7, depth=2, n_pde=0, n_obs=1, n_gh=0, n_anc=0)
+    ctx = ctx_of(pkg, pb, graph=True)
+    L, g = gpu_loss_grad(ctx)
+    Lr, gr = oracle_loss_grad(orc, pb)
+    assert_close(g[0], gr, TOL_GRAD, "grad")
+    assert_close(L[0], Lr, TOL_LOSS, "loss")
+    ctx.close()
+
+
+def test_invalid_arguments_rejected(pkg):
+    pb = wl.tiny(dim=2, width=5, depth=2)
+    with pytest.raises(pkg.PinnError) as e:
+        pb.width = 129
+        ctx_of(pkg, wl.tiny(dim=2, width=129, depth=1))
+    assert "UNSUPPORTED" in str(e.value)
+    ctx = ctx_of(pkg, wl.tiny(dim=2, width=5, depth=2), graph=False)
+    with pytest.raises(pkg.PinnError):
+        ctx.step(0, update=True)
+    with pytest.raises(pkg.PinnError):
+        ctx.query(torch.zeros(4, 3, device="cuda"), sub=5)
+    ctx.close()

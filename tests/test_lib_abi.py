@@ -1,0 +1,68 @@
+"""The C-ABI library loads and exports every entry point include/*.h declares
+(no compute calls: this runs without a GPU)."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(pinn_[a-z_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_four_core_calls():
+    names = declared_symbols()
+    for n in ("pinn_create", "pinn_step", "pinn_query", "pinn_destroy"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2602_15883_amd.abi as abi
+    if not os.path.exists(abi.LIB_PATH):
+        pytest.skip("libddpinn.so not built")
+    lib = ctypes.CDLL(abi.LIB_PATH)
+    names = declared_symbols()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(abi.EXPORTS) == names
+
+
+def test_binding_loads_and_host_only_calls_work():
+    import paper_2602_15883_amd as P
+    import workloads as wl
+    if not os.path.exists(P.abi.LIB_PATH):
+        pytest.skip("libddpinn.so not built")
+    assert P.num_params(2, 50, 4) == wl.n_params(2, 50, 4)
+    assert P.num_params(3, 128, 8) == 116740
+    assert P.lib().pinn_num_params(1, 5, 5) == -1
+
+
+def test_size_query_rejects_bad_arguments_before_any_device_work():
+    """Argument validation happens on the host before anything is enqueued."""
+    import paper_2602_15883_amd.abi as abi
+    if not os.path.exists(abi.LIB_PATH):
+        pytest.skip("libddpinn.so not built")
+    L = abi.lib()
+    cfg = abi.PinnConfig()
+    cfg.dim, cfg.width, cfg.depth, cfg.n_sub = 4, 10, 2, 1
+    sub = (abi.PinnSubdomain * 1)()
+    n = ctypes.c_size_t(0)
+    st = L.pinn_create(ctypes.byref(cfg), sub, None, ctypes.byref(n), None, None)
+    assert st == abi.PINN_E_INVAL
+    assert b"dim" in L.pinn_last_error()
+    cfg.dim, cfg.width = 2, 200
+    assert L.pinn_create(ctypes.byref(cfg), sub, None, ctypes.byref(n), None, None) == abi.PINN_E_UNSUPPORTED
+    cfg.width, cfg.beta1, cfg.beta2, cfg.eps = 10, 0.9, 0.999, 1e-8
+    # theta NULL
+    assert L.pinn_create(ctypes.byref(cfg), sub, None, ctypes.byref(n), None, None) == abi.PINN_E_INVAL
+    assert b"theta" in L.pinn_last_error()
