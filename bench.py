@@ -1,0 +1,267 @@
+#!/usr/bin/env python
+"""Benchmark of the fused subdomain training step on one MI355X.
+
+Prints ONE JSON line.  `value` is collocation points per second of the whole
+fused training step (forward with first and second derivative channels,
+Navier-Stokes residuals, losses, hand-written adjoint, gradient reduction and
+Adam), inputs resident in HBM, timed over exactly --steps hipGraph replays
+after --warmup untimed ones.  The line also carries:
+
+  roofline      the fused step kernel's algorithmic FP32 FLOPs per launch
+                divided by its average launch duration (HIP events around the
+                kernel on its own stream, same workload), against the FP32
+                MFMA peak, plus HBM traffic from rocprofv3 counters when a
+                matching profile is committed under profiles/
+  cpu_baseline  the FP64 oracle timed on this host's cores on a bounded
+                sample of the same workload (a baseline, not the target)
+  query         p50/p99 latency and points/s of the continuous-batching query
+                server (16 resident 3->8x100->3 networks, Poisson arrivals)
+
+Only one GPU is used: --gpus above 1 exits with a message.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    "config1": "config1_2d_4x50_2k",
+    "config2": "config2_2d_8x100_100k",
+    "config3": "config3_16x2d_6x64",
+    "config4": "config4_3d_8x128_250k",
+}
+
+
+def flops_per_point(dim, W, H, C):
+    """Algorithmic FLOPs of one point with C channels: 3 x forward GEMM FLOPs
+    (forward, input adjoint, weight gradient) at the true width."""
+    D = dim + 1
+    return 3 * (2 * D * W + 2 * C * W * W * (H - 1) + 2 * C * W * D)
+
+
+def step_flops(pb):
+    C = 2 * pb.dim + 2
+    fc = flops_per_point(pb.dim, pb.width, pb.depth, C)
+    fv = flops_per_point(pb.dim, pb.width, pb.depth, 1)
+    n_pde = sum(s.pde_x.shape[0] for s in pb.subs)
+    n_val = sum(s.obs_x.shape[0] + s.gh_x.shape[0] + s.anc_x.shape[0] for s in pb.subs)
+    return n_pde * fc + n_val * fv, fc
+
+
+def algorithmic_bytes(pb):
+    """Inputs the step must read plus parameter/moment/gradient traffic:
+    points and targets once, theta/m/v read and written, gradient once."""
+    D = pb.dim + 1
+    b = 0
+    for s in pb.subs:
+        b += s.pde_x.size * 4 + s.obs_x.size * 4 + s.obs_u.size * 4
+        b += s.gh_x.size * 4 + s.gh_up.size * 4 + s.gh_kind.size + s.anc_x.size * 4 + s.anc_p.size * 4
+        b += 7 * s.theta.size * 4
+    return b
+
+
+def make_problem(name, seed=0):
+    import workloads as wl
+    return {"config1": wl.config1, "config2": wl.config2, "config3": wl.config3,
+            "config4": wl.config4}[name](seed)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("ddpinn_kernels.hip", "ddpinn_internal.h"):
+        with open(os.path.join(ROOT, "paper_2602_15883_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload):
+    """HBM bytes per launch of the fused kernel from committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            tab = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = tab.get(workload)
+    if not e or e.get("kernel_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def cpu_baseline(pb, budget_s=12.0):
+    """FP64 oracle (loss + gradient + Adam) on a bounded prefix of the workload,
+    sized to roughly budget_s seconds from a short calibration run."""
+    import oracle
+    cores = oracle.threads(0)
+    s = pb.subs[0]
+    n_all = s.pde_x.shape[0]
+    frac_obs = s.obs_x.shape[0] / max(n_all, 1)
+    frac_gh = s.gh_x.shape[0] / max(n_all, 1)
+
+    def run(n):
+        no, ng = int(round(n * frac_obs)), int(round(n * frac_gh))
+        t0 = time.perf_counter()
+        L, g = oracle.loss_grad(pb.dim, pb.width, pb.depth, pb.nu, pb.lam, s.theta,
+                                is_master=s.is_master, pde_x=s.pde_x[:n], obs_x=s.obs_x[:no],
+                                obs_u=s.obs_u[:no], gh_x=s.gh_x[:ng], gh_up=s.gh_up[:ng],
+                                gh_kind=s.gh_kind[:ng], anc_x=s.anc_x, anc_p=s.anc_p)
+        oracle.adam(s.theta, np.zeros(g.size), np.zeros(g.size), g, 1, lr=pb.lr)
+        return time.perf_counter() - t0, no, ng
+
+    n0 = min(n_all, 256)
+    t0, _, _ = run(n0)
+    n = int(min(n_all, max(n0, n0 * budget_s / max(t0, 1e-3))))
+    dt, no, ng = run(n)
+    return {"value": n / dt, "unit": "collocation pts/s", "cores": cores, "kind": "oracle",
+            "sample": (f"first {n} of {n_all} collocation points of subdomain 0 with {no} "
+                       f"observation and {ng} ghost points (same per-point mix), one step: "
+                       f"FP64 loss, gradient and Adam, {dt:.1f} s")}
+
+
+def query_bench(seconds, seed=0, rate=200.0, budget=32 << 30):
+    import torch
+
+    import workloads as wl
+    from paper_2602_15883_amd.serve import QueryServer, Request, latency_stats, serving_context
+    boxes, thetas = wl.serving_nets(seed, width=100, depth=8)
+    ctx = serving_context(boxes, thetas, 100, 8, device="cuda")
+    n_req = max(1, int(seconds * rate))
+    arrivals, sizes = wl.query_requests(seed, n_req, rate_hz=rate)
+    rng = np.random.default_rng([seed, 9])
+    pool = wl.query_points(rng, int(min(sizes.sum(), 4_000_000)))
+    reqs, o = [], 0
+    for i in range(n_req):
+        n = int(sizes[i])
+        if o + n > pool.shape[0]:
+            o = 0
+        reqs.append(Request(i, float(arrivals[i]), pool[o:o + n]))
+        o += n
+    srv = QueryServer(ctx, hbm_budget_bytes=budget, n_streams=4, max_batch_points=1 << 20)
+    # warm-up: a few requests through the same path
+    warm = [Request(-1 - i, 0.0, pool[:1000 * (i + 1)]) for i in range(4)]
+    srv.run(warm)
+    srv.busy_intervals.clear()
+    wall = srv.run(reqs)
+    st = latency_stats(reqs)
+    busy = srv.busy_seconds()
+    ctx.close()
+    st.update({"points_per_s": st["points"] / wall, "wall_s": wall, "rate_hz": rate,
+               "gpu_busy_frac": busy / wall, "workload": "16 x 2d 3->8x100->3, Poisson 200 req/s, "
+               "1-200000 pts/request log-uniform, 4 streams, 32 GB budget"})
+    return st
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--tile-points", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--query-seconds", type=float, default=8.0)
+    ap.add_argument("--no-query", action="store_true")
+    ap.add_argument("--per-subdomain", action="store_true",
+                    help="also time one plain launch per subdomain (grouped vs plain)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(subdomains are grouped inside one launch on one device)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2602_15883_amd as P
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    pb = make_problem(args.workload, args.seed)
+    flops, fc = step_flops(pb)
+    n_pde = pb.n_pde
+    ctx = P.context_from_problem(pb, device="cuda:0", graph=True, tile_points=args.tile_points)
+    info = ctx.launch_info()
+    stream = torch.cuda.current_stream()
+
+    # ---- throughput: graph replays of the whole step
+    for t in range(1, args.warmup + 1):
+        ctx.step(t)
+    torch.cuda.synchronize()
+    t_begin = time.perf_counter()
+    for t in range(args.warmup + 1, args.warmup + args.steps + 1):
+        ctx.step(t)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_begin
+    ms_per_step = elapsed / args.steps * 1e3
+    value = n_pde * args.steps / elapsed
+    loss = ctx._loss.cpu().numpy()
+    finite = bool(np.all(np.isfinite(loss)))
+
+    # ---- roofline: HIP events around the fused kernel launches, same workload
+    base_t = args.warmup + args.steps
+    ctx.kernel_time()
+    for k in range(args.steps):
+        ctx.step(base_t + 1 + k, time_kernel=True)
+    k_ms, k_n = ctx.kernel_time()
+    k_avg_ms = k_ms / max(k_n, 1)
+    achieved = flops / (k_avg_ms * 1e-3) / 1e12
+    traffic = traffic_from_profiles(args.workload)
+
+    extra = {}
+    if args.per_subdomain and len(pb.subs) > 1:
+        ctx.kernel_time()
+        for k in range(args.steps):
+            ctx.step(base_t + args.steps + 1 + k, time_kernel=True, per_subdomain=True)
+        p_ms, p_n = ctx.kernel_time()
+        extra["grouped_vs_plain"] = {"grouped_kernel_ms": k_avg_ms, "plain_launches_ms": p_ms / max(p_n, 1),
+                                     "speedup": (p_ms / max(p_n, 1)) / k_avg_ms}
+    ctx.close()
+
+    out = {
+        "metric": "collocation pts/s per fused train step (fwd+2nd-deriv+bwd); query p50/p99 ms",
+        "value": value,
+        "unit": "collocation pts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "dim": pb.dim, "width": pb.width,
+                   "depth": pb.depth, "n_sub": len(pb.subs), "n_pde": n_pde,
+                   "n_value_points": int(sum(s.obs_x.shape[0] + s.gh_x.shape[0] + s.anc_x.shape[0]
+                                             for s in pb.subs)),
+                   "gflop_per_step": flops / 1e9, "tile_points": info["tile_points"],
+                   "workgroups": info["n_wg"], "graph": True, "losses_finite": finite},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+                     "traffic": traffic, "kernel": "step_kernel", "kernel_ms": k_avg_ms,
+                     "launches_timed": k_n, "flop_per_launch": flops,
+                     "flop_per_collocation_point": fc},
+    }
+    out.update(extra)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(pb)
+    if not args.no_query:
+        out["query"] = query_bench(args.query_seconds, seed=args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

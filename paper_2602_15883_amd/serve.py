@@ -1,0 +1,197 @@
+"""Continuous-batching query server over resident subdomain networks.
+
+Stitching of local experts (section 3): every query point is evaluated by the
+subdomain network whose box contains it; the server returns (u, v, p) and the
+vorticity v_x - u_y.  All networks stay resident on the GPU.  Requests arrive
+open loop; a dispatcher admits them while earlier batches are still on the
+GPU (as long as the HBM budget allows), packs whole requests into batches and
+issues each batch on one of several HIP streams: host-to-device copy, routed
+query (pinn_query), device-to-host copy, completion event.  Per-point results
+do not depend on the batch a point lands in, so a request's result is the same
+alone and in the mix.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from .context import Context, SubTensors
+
+BYTES_PER_POINT = 3 * 4 + 4 * 4 + 2 * 4   # points in, (u, v, p, w) out, routing scratch
+
+
+def serving_context(boxes, thetas, width: int, depth: int, dim: int = 2, nu: float = 0.01,
+                    device="cuda", max_query_points: int = 1 << 22) -> Context:
+    """A context holding only resident networks (no training data)."""
+    subs = []
+    dev = torch.device(device)
+    D = dim + 1
+    for s, th in enumerate(thetas):
+        t = torch.from_numpy(np.ascontiguousarray(th, np.float32)).to(dev)
+        eD = torch.zeros(0, D, device=dev)
+        subs.append(SubTensors(lo=list(boxes[s][0]), hi=list(boxes[s][1]), is_master=False,
+                               theta=t, adam_m=torch.zeros_like(t), adam_v=torch.zeros_like(t),
+                               pde_x=eD, obs_x=eD, obs_u=torch.zeros(0, dim, device=dev),
+                               gh_x=eD, gh_up=eD,
+                               gh_kind=torch.zeros(0, dtype=torch.uint8, device=dev),
+                               anc_x=eD, anc_p=torch.zeros(0, device=dev)))
+    return Context(dim, width, depth, subs, nu, np.zeros(6), graph=False, device=dev,
+                   max_query_points=max_query_points)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival: float                 # scheduled arrival (s, relative to start)
+    x: np.ndarray                  # [n, 3] float32 host points
+    out: Optional[np.ndarray] = None
+    done: float = -1.0             # completion visible on host (s)
+    admitted: float = -1.0
+
+
+@dataclass
+class _Batch:
+    reqs: List[Request]
+    n: int
+    slot: int
+    event: torch.cuda.Event
+    start_ev: torch.cuda.Event
+    keep: list = field(default_factory=list)
+    nbytes: int = 0
+
+
+class QueryServer:
+    """Open-loop, continuously batching server over one Context."""
+
+    def __init__(self, ctx: Context, hbm_budget_bytes: int = 32 << 30, n_streams: int = 4,
+                 max_batch_points: int = 1 << 20, min_batch_points: int = 1):
+        self.ctx = ctx
+        self.budget = int(hbm_budget_bytes)
+        self.max_batch = int(max_batch_points)
+        self.streams = [torch.cuda.Stream(device=ctx.device) for _ in range(n_streams)]
+        self.free_slots = deque(range(n_streams))
+        cap = self.max_batch
+        self.h_in = [torch.empty(cap, 3, dtype=torch.float32, pin_memory=True) for _ in range(n_streams)]
+        self.h_out = [torch.empty(cap, 4, dtype=torch.float32, pin_memory=True) for _ in range(n_streams)]
+        self.inflight: List[_Batch] = []
+        self.inflight_bytes = 0
+        self.busy_intervals = []
+        self.deferred = 0
+
+    def request_bytes(self, n: int) -> int:
+        return n * BYTES_PER_POINT + self.ctx.query_scratch_bytes(0) + 4096
+
+    # -------------------------------------------------------------- dispatch
+    def _launch(self, reqs: List[Request], t0: float):
+        slot = self.free_slots.popleft()
+        s = self.streams[slot]
+        n = sum(len(r.x) for r in reqs)
+        hin, hout = self.h_in[slot], self.h_out[slot]
+        o = 0
+        for r in reqs:
+            hin[o:o + len(r.x)].numpy()[:] = r.x
+            o += len(r.x)
+        with torch.cuda.stream(s):
+            start_ev = torch.cuda.Event(enable_timing=True)
+            start_ev.record(s)
+            x = torch.empty(n, 3, dtype=torch.float32, device=self.ctx.device)
+            x.copy_(hin[:n], non_blocking=True)
+            out = torch.empty(n, 4, dtype=torch.float32, device=self.ctx.device)
+            scratch = torch.empty(self.ctx.query_scratch_bytes(n) + 256, dtype=torch.uint8,
+                                  device=self.ctx.device)
+            self.ctx.query(x, sub=-1, what="uvpw", out=out, scratch=scratch, stream=s)
+            hout[:n].copy_(out, non_blocking=True)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(s)
+        b = _Batch(reqs=reqs, n=n, slot=slot, event=ev, start_ev=start_ev, keep=[x, out, scratch])
+        b.nbytes = sum(self.request_bytes(len(r.x)) for r in reqs)
+        self.inflight.append(b)
+
+    def _poll(self, t0: float) -> int:
+        done = 0
+        still = []
+        for b in self.inflight:
+            if b.event.query():
+                now = time.perf_counter() - t0
+                hout = self.h_out[b.slot]
+                o = 0
+                for r in b.reqs:
+                    r.out = hout[o:o + len(r.x)].numpy().copy()
+                    o += len(r.x)
+                    r.done = now
+                self.busy_intervals.append((b.start_ev, b.event))
+                self.inflight_bytes -= b.nbytes
+                self.free_slots.append(b.slot)
+                done += len(b.reqs)
+            else:
+                still.append(b)
+        self.inflight = still
+        return done
+
+    def run(self, requests: List[Request], time_scale: float = 1.0, idle_sleep: float = 2e-5):
+        """Serve `requests` (sorted by arrival) open loop; returns wall seconds."""
+        for r in requests:
+            if self.request_bytes(len(r.x)) > self.budget:
+                raise ValueError(f"request {r.rid} of {len(r.x)} points exceeds the HBM budget")
+            if len(r.x) > self.max_batch:
+                raise ValueError(f"request {r.rid} exceeds max_batch_points")
+        pending = deque(requests)
+        waiting: deque = deque()
+        remaining = len(requests)
+        t0 = time.perf_counter()
+        while remaining:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival * time_scale <= now:
+                waiting.append(pending.popleft())
+            remaining -= self._poll(t0)
+            # admission: whole requests, oldest first, while memory and a stream are free
+            while waiting and self.free_slots:
+                batch, n, nbytes = [], 0, 0
+                while waiting:
+                    r = waiting[0]
+                    rb = self.request_bytes(len(r.x))
+                    if n + len(r.x) > self.max_batch or self.inflight_bytes + nbytes + rb > self.budget:
+                        break
+                    batch.append(waiting.popleft())
+                    n += len(r.x)
+                    nbytes += rb
+                if not batch:
+                    self.deferred += 1
+                    break
+                for r in batch:
+                    r.admitted = now
+                self.inflight_bytes += nbytes
+                self._launch(batch, t0)
+            if remaining and not (waiting and self.free_slots):
+                time.sleep(idle_sleep)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    def busy_seconds(self) -> float:
+        """Union of the batches' device intervals (from their events)."""
+        if not self.busy_intervals:
+            return 0.0
+        base = self.busy_intervals[0][0]
+        iv = sorted((base.elapsed_time(a) / 1e3, base.elapsed_time(b) / 1e3)
+                    for a, b in self.busy_intervals)
+        tot, cs, ce = 0.0, iv[0][0], iv[0][1]
+        for a, b in iv[1:]:
+            if a > ce:
+                tot += ce - cs
+                cs, ce = a, b
+            else:
+                ce = max(ce, b)
+        return tot + ce - cs
+
+
+def latency_stats(requests: List[Request], time_scale: float = 1.0) -> dict:
+    lat = np.array([(r.done - r.arrival * time_scale) * 1e3 for r in requests])
+    pts = sum(len(r.x) for r in requests)
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "p999_ms": float(np.percentile(lat, 99.9)), "mean_ms": float(lat.mean()),
+            "requests": len(requests), "points": int(pts)}
