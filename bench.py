@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_MFMA_TFLOPS = 157.3     # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0
+COPY_BYTES = 256 << 20            # size of the counter-calibration copy (each way)
 
 WORKLOADS = {
     "config1": "config1_2d_4x50_2k",
@@ -177,6 +178,9 @@ def main():
     ap.add_argument("--no-query", action="store_true")
     ap.add_argument("--per-subdomain", action="store_true",
                     help="also time one plain launch per subdomain (grouped vs plain)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain elementwise copy of 256 MiB (reads and writes "
+                         "268435456 bytes) three times, for scaling HBM counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -189,6 +193,13 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     pb = make_problem(args.workload, args.seed)
     flops, fc = step_flops(pb)
     n_pde = pb.n_pde

@@ -141,7 +141,7 @@ struct pinn_ctx {
   // per-subdomain launches
   std::vector<int> ps_wg, ps_wgb_off;
   int ps_items = 0, ps_seg = 0;
-  int n_slabs = 0;
+  int n_slabs = 0, n_chunks = 1;
   int64_t stash_per_wg = 0;
   // device regions inside the workspace
   SubDev* d_subs = nullptr;
@@ -154,6 +154,7 @@ struct pinn_ctx {
   float* d_slabs = nullptr;
   float* d_stash = nullptr;
   float* d_frag = nullptr;
+  float* d_partial = nullptr;
   float* d_loss_ws = nullptr;
   int32_t* d_flag = nullptr;
   float* d_boxes = nullptr;
@@ -358,6 +359,12 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
     c->ps_items = (int)items_ps.size();
   }
   c->n_slabs = std::max(std::max(c->n_seg, c->ps_seg), 1);
+  int max_seg_sub = 1;
+  for (int s = 0; s < c->n_sub; ++s) {
+    max_seg_sub = std::max(max_seg_sub, seg_begin[s + 1] - seg_begin[s]);
+    max_seg_sub = std::max(max_seg_sub, seg_ps[s + 1] - seg_ps[s]);
+  }
+  c->n_chunks = (max_seg_sub + kSlabChunk - 1) / kSlabChunk;
   const int stash_wg = std::max(c->n_wg, 1);
   const int NCB = (2 * sh.dim + 2) * (c->tile_points / 16);
   c->stash_per_wg = (int64_t)sh.NW * sh.H * NCB * 256;
@@ -381,6 +388,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   const size_t o_seg_ps = take(sizeof(int32_t) * (c->n_sub + 1));
   const size_t o_slabs = take(sizeof(float) * (size_t)c->n_slabs * sh.slab_floats);
   const size_t o_stash = take(sizeof(float) * (size_t)stash_wg * c->stash_per_wg);
+  const size_t o_partial = take(sizeof(float) * (size_t)c->n_sub * c->n_chunks * sh.slab_floats);
   const size_t o_frag = take(sizeof(float) * (size_t)c->n_sub * sh.frag_floats);
   const size_t o_loss = take(sizeof(float) * 8 * c->n_sub);
   const size_t o_flag = take(64);
@@ -406,6 +414,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->d_slabs = (float*)(ws + o_slabs);
   c->d_stash = (float*)(ws + o_stash);
   c->d_frag = (float*)(ws + o_frag);
+  c->d_partial = (float*)(ws + o_partial);
   c->d_loss_ws = (float*)(ws + o_loss);
   c->d_flag = (int32_t*)(ws + o_flag);
   c->d_boxes = (float*)(ws + o_boxes);
@@ -478,6 +487,8 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->rargs.subs = c->d_subs;
   c->rargs.seg_begin = c->d_seg_begin;
   c->rargs.slabs = c->d_slabs;
+  c->rargs.partial = c->d_partial;
+  c->rargs.n_chunks = c->n_chunks;
   c->rargs.loss_ws = c->d_loss_ws;
   c->rargs.n_sub = c->n_sub;
   c->rargs.lr = cfg->lr;
@@ -509,11 +520,17 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
     c->rargs.t = 1;
     c->rargs.update = 0;
     void* ra[] = {&c->rargs};
+    hipKernelNodeParams kq{};
+    grid_slab_sum(c->rargs, &kq.gridDim, &kq.blockDim);
+    kq.func = (void*)slab_sum_kernel_ptr();
+    kq.kernelParams = ra;
+    hipGraphNode_t n25;
+    HIPCHECK(hipGraphAddKernelNode(&n25, gr, &n2, 1, &kq));
     hipKernelNodeParams kr{};
     grid_reduce(c->rargs, &kr.gridDim, &kr.blockDim);
     kr.func = (void*)reduce_kernel_ptr();
     kr.kernelParams = ra;
-    HIPCHECK(hipGraphAddKernelNode(&n3, gr, &n2, 1, &kr));
+    HIPCHECK(hipGraphAddKernelNode(&n3, gr, &n25, 1, &kr));
     HIPCHECK(hipGraphAddKernelNode(&n4, gr, &n3, 1, &kp));
     c->graph = gr;
     c->n_reduce = n3;

@@ -10,6 +10,7 @@ constexpr int kWave = 64;
 constexpr int kMaxWidth = 128;
 constexpr int kMaxDepth = 16;
 constexpr int kMaxSub = 4096;
+constexpr int kSlabChunk = 16;   // slabs summed per thread in the first reduce stage
 
 // Per-subdomain device descriptor (copied into the workspace at create).
 struct SubDev {
@@ -90,6 +91,8 @@ struct ReduceArgs {
   const SubDev* subs;
   const int32_t* seg_begin; // [n_sub + 1] slab range of each subdomain
   const float* slabs;
+  float* partial;           // [n_sub][n_chunks][slab_floats] first-stage sums
+  int32_t n_chunks;         // ceil(max slabs of one subdomain / kSlabChunk)
   float* loss_out;          // [n_sub][7] or null
   float* grad_out;          // [n_sub][P] or null
   float* loss_ws;           // [n_sub][8] always written (finite check)
@@ -170,6 +173,8 @@ hipError_t launch_nonfinite_check(const float* loss_ws, int n_sub, int32_t* flag
 const void* step_kernel_ptr(int dim, int tile_points);
 const void* prep_kernel_ptr();
 const void* reduce_kernel_ptr();
+const void* slab_sum_kernel_ptr();
+void grid_slab_sum(const ReduceArgs& a, dim3* grid, dim3* block);
 int step_lds_floats(const Shape& sh, int tile_points);
 int query_lds_floats(const Shape& sh);
 int step_value_points(int dim, int tile_points);

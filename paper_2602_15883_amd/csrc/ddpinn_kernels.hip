@@ -28,7 +28,8 @@
 //   Hbar_{l-1} = W_l^T Zbar run on MFMA.  Each workgroup accumulates its
 //   gradient contribution in a private slab (one per (workgroup, subdomain)
 //   segment); a second kernel sums the slabs in a fixed order and applies
-//   Adam.  No float atomics: results are bitwise reproducible.
+//   Adam.  No float atomics: every slab float has one writer lane and the sum
+//   order is fixed, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -45,6 +46,37 @@ __device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
 }
 
 __device__ __forceinline__ v4f zero4() { return v4f{0.f, 0.f, 0.f, 0.f}; }
+
+// Accesses to device memory through the global address space: generic
+// (flat) accesses would also count against the LDS wait counter, so every
+// LDS wait would also wait for outstanding memory loads.
+#define GLOBAL_AS __attribute__((address_space(1)))
+__device__ __forceinline__ v4f ldg4(const float* p) { return *(const GLOBAL_AS v4f*)p; }
+__device__ __forceinline__ float ldg(const float* p) { return *(const GLOBAL_AS float*)p; }
+__device__ __forceinline__ void stg4(float* p, v4f v) { *(GLOBAL_AS v4f*)p = v; }
+__device__ __forceinline__ void stg(float* p, float v) { *(GLOBAL_AS float*)p = v; }
+
+// tanh without branches, from two textbook forms:
+//   |x| < 0.4 : x * P(x^2), P = Maclaurin series of tanh(x)/x through the x^12
+//               term (the first omitted term is below 4e-9 relative)
+//   otherwise : sign(x) * (1 - 2 / (exp(2|x|) + 1)), hardware exp2 and rcp
+// Within ~3 ulp of the exact value over the whole float range (the float32
+// error of this scheme is pinned on the CPU).
+__device__ __forceinline__ float tanh_f32(float x) {
+  const float a = fabsf(x);
+  const float u = x * x;
+  float p = 3.5921280365724810e-3f;          //  21844/6081075
+  p = fmaf(p, u, -8.8632355299021966e-3f);   // -1382/155925
+  p = fmaf(p, u, 2.1869488536155203e-2f);    //  62/2835
+  p = fmaf(p, u, -5.3968253968253968e-2f);   // -17/315
+  p = fmaf(p, u, 1.3333333333333333e-1f);    //  2/15
+  p = fmaf(p, u, -3.3333333333333333e-1f);   // -1/3
+  p = fmaf(p, u, 1.f);
+  const float small = x * p;
+  const float e = __builtin_amdgcn_exp2f(a * 2.8853900817779268f);   // exp(2|x|)
+  const float big = __builtin_copysignf(fmaf(-2.f, __builtin_amdgcn_rcpf(e + 1.f), 1.f), x);
+  return a < 0.4f ? small : big;
+}
 
 // Channel layout of a tile in a given mode.
 //   M_PDE  : CM = 2d+2 channels: 0 value, 1..d d/dx_j, d+1 d/dt, d+2..2d+1 d2/dx_j^2
@@ -73,7 +105,7 @@ __device__ __forceinline__ void act_forward(v4f (&a)[NCB]) {
   for (int pb = 0; pb < NPB; ++pb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float s = tanhf(a[pb][i]);
+      const float s = tanh_f32(a[pb][i]);
       const float s1 = 1.f - s * s;
       if constexpr (MODE == M_PDE) {
         const float s2 = -2.f * s * s1;
@@ -94,6 +126,34 @@ __device__ __forceinline__ void act_forward(v4f (&a)[NCB]) {
   }
 }
 
+// h = act(z) of a stashed pre-activation stack, written straight into the
+// neuron-major LDS layout [neuron][column] (stride S2) used by the dW GEMM.
+template <int DIM, int NCB, int MODE>
+__device__ __forceinline__ void act_store_bwd(float* buf, int S2, const v4f (&z)[NCB], int w, int g, int j) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int NPB = M::NPB;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float* row = buf + (16 * w + 4 * g + i) * S2 + j;
+#pragma unroll
+    for (int pb = 0; pb < NPB; ++pb) {
+      const float s = tanh_f32(z[pb][i]);
+      const float s1 = 1.f - s * s;
+      row[16 * pb] = s;
+      if constexpr (MODE == M_PDE) {
+        const float s2 = -2.f * s * s1;
+#pragma unroll
+        for (int jj = 0; jj <= DIM; ++jj) row[16 * ((1 + jj) * NPB + pb)] = s1 * z[(1 + jj) * NPB + pb][i];
+#pragma unroll
+        for (int jj = 0; jj < DIM; ++jj) {
+          const float z1 = z[(1 + jj) * NPB + pb][i];
+          row[16 * ((DIM + 2 + jj) * NPB + pb)] = s2 * z1 * z1 + s1 * z[(DIM + 2 + jj) * NPB + pb][i];
+        }
+      }
+    }
+  }
+}
+
 // Adjoint of act_forward: hb (dL/dh) -> dL/dz in place; zs holds z.
 //   zbar_jj = s1 hbar_jj
 //   zbar_j  = s1 hbar_j + 2 s2 z_j hbar_jj      (spatial j; time: s1 hbar_t)
@@ -107,7 +167,7 @@ __device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]
   for (int pb = 0; pb < NPB; ++pb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float s = tanhf(zs[pb][i]);
+      const float s = tanh_f32(zs[pb][i]);
       const float s1 = 1.f - s * s;
       if constexpr (MODE == M_PDE) {
         const float s2 = -2.f * s * s1;
@@ -152,10 +212,9 @@ __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const
                                           int S, int K4, int g, int j, int lane,
                                           v4f (&acc)[NCB]) {
   const float* bb = bufB + j * S + g * (4 * K4);
-  const v4f* ap = reinterpret_cast<const v4f*>(afrag) + lane;
-#pragma unroll 2
+  const float* ap = afrag + lane * 4;
   for (int s4 = 0; s4 < K4; ++s4) {
-    const v4f a = ap[s4 * 64];
+    const v4f a = ldg4(ap + s4 * 256);
     v4f b[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
@@ -167,28 +226,25 @@ __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const
   }
 }
 
-// dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col]
+// dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col], t < NNB
 //   Zbar from bufG ([col][neuron], stride S); Hprev from bufHb ([neuron][col], stride S2)
 //   K index of step s in lane group g: g*4*NCB + s
-template <int NCB>
+template <int NCB, int NNB>
 __device__ __forceinline__ void gemm_dw(const float* bufG, int S, const float* bufHb, int S2,
-                                        int w, int g, int j, int nb0, int nnb, v4f (&dw)[4]) {
+                                        int w, int g, int j, int nb0, v4f (&dw)[4]) {
   const float* ab = bufG + (g * 4 * NCB) * S + 16 * w + j;
   const float* bb = bufHb + (16 * nb0 + j) * S2 + g * 4 * NCB;
-#pragma unroll 2
   for (int s4 = 0; s4 < NCB; ++s4) {
     float a[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[q] = ab[(4 * s4 + q) * S];
-    v4f b[4];
+    v4f b[NNB];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      b[t] = (t < nnb) ? *reinterpret_cast<const v4f*>(bb + t * 16 * S2 + 4 * s4) : zero4();
+    for (int t = 0; t < NNB; ++t) b[t] = *reinterpret_cast<const v4f*>(bb + t * 16 * S2 + 4 * s4);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int t = 0; t < 4; ++t)
-        if (t < nnb) dw[t] = mfma4(a[q], b[t][q], dw[t]);
+      for (int t = 0; t < NNB; ++t) dw[t] = mfma4(a[q], b[t][q], dw[t]);
   }
 }
 
@@ -218,8 +274,8 @@ __device__ __forceinline__ void input_layer(v4f (&a)[NCB], const float* __restri
     const int r = 16 * w + 4 * g + i;
     float wr[D];
 #pragma unroll
-    for (int q = 0; q < D; ++q) wr[q] = W1p[r * D + q];
-    const float br = b1p[r];
+    for (int q = 0; q < D; ++q) wr[q] = ldg(W1p + r * D + q);
+    const float br = ldg(b1p + r);
 #pragma unroll
     for (int pb = 0; pb < NPB; ++pb) {
       const float* xp = xin + (16 * pb + j) * D;
@@ -251,7 +307,7 @@ __device__ __forceinline__ void store_fwd(float* buf, int S, const v4f (&a)[NCB]
 // add the bias to the value-channel column blocks
 template <int NCB, int NPB>
 __device__ __forceinline__ void add_bias(v4f (&a)[NCB], const float* __restrict__ b, int w, int g) {
-  const v4f bv = *reinterpret_cast<const v4f*>(b + 16 * w + 4 * g);
+  const v4f bv = ldg4(b + 16 * w + 4 * g);
 #pragma unroll
   for (int pb = 0; pb < NPB; ++pb) a[pb] += bv;
 }
@@ -270,13 +326,13 @@ __device__ __forceinline__ void output_layer(const float* bufH, int S, int Wp,
     float acc = 0.f;
     for (int n = 0; n < Wp; n += 4) {
       const v4f h4 = *reinterpret_cast<const v4f*>(hr + n);
-      const v4f w4 = *reinterpret_cast<const v4f*>(wo + n);
+      const v4f w4 = ldg4(wo + n);
       acc += h4[0] * w4[0];
       acc += h4[1] * w4[1];
       acc += h4[2] * w4[2];
       acc += h4[3] * w4[3];
     }
-    if (col < 16 * M::NPB) acc += bop[o];
+    if (col < 16 * M::NPB) acc += ldg(bop + o);
     ys[o * NCOL + col] = acc;
   }
 }
@@ -389,7 +445,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     if (pde) {
       for (int k = tid; k < MP::NPTS * D; k += nthr) {
         const int pt = k / D;
-        xin[k] = (pt < item.count) ? sd.pde_x[(size_t)(item.start + pt) * D + (k - pt * D)] : 0.f;
+        xin[k] = (pt < item.count) ? ldg(sd.pde_x + (size_t)(item.start + pt) * D + (k - pt * D)) : 0.f;
       }
     } else {
       for (int k = tid; k < NCOL * D; k += nthr) {
@@ -397,9 +453,9 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         float v = 0.f;
         if (pt < item.count) {
           int idx = item.start + pt;
-          if (idx < sd.n_obs) v = sd.obs_x[(size_t)idx * D + q];
-          else if ((idx -= sd.n_obs) < sd.n_gh) v = sd.gh_x[(size_t)idx * D + q];
-          else v = sd.anc_x[(size_t)(idx - sd.n_gh) * D + q];
+          if (idx < sd.n_obs) v = ldg(sd.obs_x + (size_t)idx * D + q);
+          else if ((idx -= sd.n_obs) < sd.n_gh) v = ldg(sd.gh_x + (size_t)idx * D + q);
+          else v = ldg(sd.anc_x + (size_t)(idx - sd.n_gh) * D + q);
         }
         xin[k] = v;
       }
@@ -412,7 +468,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
-      reinterpret_cast<v4f*>(stash_w)[(0 * NCB + cb) * 64 + lane] = acc[cb];
+      stg4(stash_w + ((0 * NCB + cb) * 64 + lane) * 4, acc[cb]);
     if (pde) act_forward<DIM, NCB, M_PDE>(acc);
     else act_forward<DIM, NCB, M_VALUE>(acc);
     store_fwd<NCB>(bufH, S, acc, w, g, j);
@@ -428,7 +484,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
-        reinterpret_cast<v4f*>(stash_w)[((l - 1) * NCB + cb) * 64 + lane] = acc[cb];
+        stg4(stash_w + (((l - 1) * NCB + cb) * 64 + lane) * 4, acc[cb]);
       __syncthreads();
       if (pde) act_forward<DIM, NCB, M_PDE>(acc);
       else act_forward<DIM, NCB, M_VALUE>(acc);
@@ -496,7 +552,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
             float sq = 0.f;
 #pragma unroll
             for (int i = 0; i < DIM; ++i) {
-              const float d0 = y[i] - sd.obs_u[(size_t)idx * DIM + i];
+              const float d0 = y[i] - ldg(sd.obs_u + (size_t)idx * DIM + i);
               sq += d0 * d0;
               e[i] = 2.f * sd.lam[0] * sd.inv_n[1] * d0;
             }
@@ -521,7 +577,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
             }
           } else {
             idx -= sd.n_gh;
-            const float dp = y[DIM] - sd.anc_p[idx];
+            const float dp = y[DIM] - ldg(sd.anc_p + idx);
             lacc[5] += dp * dp;
             e[DIM] = 2.f * sd.lam[5] * sd.inv_n[3] * dp;
           }
@@ -532,7 +588,11 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     }
     __syncthreads();
 
-    // ---- output layer adjoint
+    // ---- output layer adjoint (z_H is fetched from the stash meanwhile)
+    v4f zs[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+      zs[cb] = ldg4(stash_w + (((H - 1) * NCB + cb) * 64 + lane) * 4);
     {
       const int npb = pde ? MP::NPB : MV::NPB;
       if (tid < D * Wp) {
@@ -551,7 +611,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         const int r = 16 * w + 4 * g + i;
         float wo[D];
 #pragma unroll
-        for (int o = 0; o < D; ++o) wo[o] = Wop[o * Wp + r];
+        for (int o = 0; o < D; ++o) wo[o] = ldg(Wop + o * Wp + r);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
           float s = 0.f;
@@ -564,10 +624,6 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     __syncthreads();
 
     // ---- hidden and input layer adjoints
-    v4f zs[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      zs[cb] = reinterpret_cast<const v4f*>(stash_w)[((H - 1) * NCB + cb) * 64 + lane];
     for (int l = H; l >= 1; --l) {
       if (pde) act_adjoint<DIM, NCB, M_PDE>(acc, zs);
       else act_adjoint<DIM, NCB, M_VALUE>(acc, zs);
@@ -620,35 +676,31 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       // recompute h_{l-1} from the stashed z_{l-1}; keep z_{l-1} for the next adjoint
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
-        zs[cb] = reinterpret_cast<const v4f*>(stash_w)[((l - 2) * NCB + cb) * 64 + lane];
-      {
-        v4f hv[NCB];
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) hv[cb] = zs[cb];
-        if (pde) act_forward<DIM, NCB, M_PDE>(hv);
-        else act_forward<DIM, NCB, M_VALUE>(hv);
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-#pragma unroll
-          for (int i = 0; i < 4; ++i) bufH[(16 * w + 4 * g + i) * S2 + 16 * cb + j] = hv[cb][i];
-      }
+        zs[cb] = ldg4(stash_w + (((l - 2) * NCB + cb) * 64 + lane) * 4);
+      if (pde) act_store_bwd<DIM, NCB, M_PDE>(bufH, S2, zs, w, g, j);
+      else act_store_bwd<DIM, NCB, M_VALUE>(bufH, S2, zs, w, g, j);
       __syncthreads();
-      // dW_l += Zbar_l H_{l-1}^T into this segment's slab
+      // dW_l += Zbar_l H_{l-1}^T into this segment's slab; the slab's current
+      // values are requested before each chunk's GEMM so the read overlaps it
       {
         float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
-        v4f* swv = reinterpret_cast<v4f*>(sw);
+        const bool first = item.flags & ITEM_FIRST;
         for (int nb0 = 0; nb0 < NW; nb0 += 4) {
           const int nnb = (NW - nb0) < 4 ? (NW - nb0) : 4;
-          v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
-          gemm_dw<NCB>(bufG, S, bufH, S2, w, g, j, nb0, nnb, dw);
+          v4f old[4];
 #pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            if (t < nnb) {
-              v4f* p = swv + (size_t)(w * NW + nb0 + t) * 64 + lane;
-              if (item.flags & ITEM_FIRST) *p = dw[t];
-              else *p = *p + dw[t];
-            }
+          for (int t = 0; t < 4; ++t)
+            old[t] = (t < nnb && !first) ? ldg4(sw + ((size_t)(w * NW + nb0 + t) * 64 + lane) * 4) : zero4();
+          v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
+          switch (nnb) {
+            case 4: gemm_dw<NCB, 4>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
+            case 3: gemm_dw<NCB, 3>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
+            case 2: gemm_dw<NCB, 2>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
+            default: gemm_dw<NCB, 1>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
           }
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (t < nnb) stg4(sw + ((size_t)(w * NW + nb0 + t) * 64 + lane) * 4, old[t] + dw[t]);
         }
       }
       // Hbar_{l-1} = W_l^T Zbar_l
@@ -757,16 +809,38 @@ __device__ __forceinline__ int64_t slab_pos(const Shape& sh, int64_t p) {
   return sh.s_bo + (p - sh.p_b[H + 1]);
 }
 
+// stage 1: partial[s][c][pos] = sum of slabs k0 + c*CH .. of subdomain s at
+// position pos (consecutive threads read consecutive floats of each slab)
+__global__ void slab_sum_kernel(const ReduceArgs a) {
+  const Shape& sh = a.sh;
+  const int s = blockIdx.y, c = blockIdx.z;
+  const int64_t pos = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= sh.slab_floats) return;
+  const int k0 = a.seg_begin[s] + c * kSlabChunk;
+  const int k1 = min(a.seg_begin[s + 1], k0 + kSlabChunk);
+  float v[kSlabChunk];
+#pragma unroll
+  for (int q = 0; q < kSlabChunk; ++q)
+    v[q] = (k0 + q < k1) ? a.slabs[(size_t)(k0 + q) * sh.slab_floats + pos] : 0.f;
+  float acc = 0.f;
+#pragma unroll
+  for (int q = 0; q < kSlabChunk; ++q) acc += v[q];
+  a.partial[((size_t)s * a.n_chunks + c) * sh.slab_floats + pos] = acc;
+}
+
+// stage 2: gradient of every parameter (partials in chunk order), Adam, losses
 __global__ void reduce_kernel(const ReduceArgs a) {
   const Shape& sh = a.sh;
   const int s = blockIdx.y;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int k0 = a.seg_begin[s], k1 = a.seg_begin[s + 1];
+  const int nseg = a.seg_begin[s + 1] - a.seg_begin[s];
+  const int nc = (nseg + kSlabChunk - 1) / kSlabChunk;
+  const float* part = a.partial + (size_t)s * a.n_chunks * sh.slab_floats;
   const SubDev& sd = a.subs[s];
   if (p < sh.P) {
     const int64_t pos = slab_pos(sh, p);
     float g = 0.f;
-    for (int k = k0; k < k1; ++k) g += a.slabs[(size_t)k * sh.slab_floats + pos];
+    for (int c = 0; c < nc; ++c) g += part[(size_t)c * sh.slab_floats + pos];
     if (a.grad_out) a.grad_out[(size_t)s * sh.P + p] = g;
     if (a.update) {
       const float m = a.beta1 * sd.m[p] + (1.f - a.beta1) * g;
@@ -783,7 +857,7 @@ __global__ void reduce_kernel(const ReduceArgs a) {
     float L[7];
     for (int q = 0; q < 6; ++q) {
       float v = 0.f;
-      for (int k = k0; k < k1; ++k) v += a.slabs[(size_t)k * sh.slab_floats + sh.s_loss + q];
+      for (int c = 0; c < nc; ++c) v += part[(size_t)c * sh.slab_floats + sh.s_loss + q];
       L[q] = v;
     }
     L[0] *= sd.inv_n[1];
@@ -1039,6 +1113,7 @@ const void* step_kernel_ptr(int dim, int tile_points) {
 }
 const void* prep_kernel_ptr() { return (const void*)prep_kernel; }
 const void* reduce_kernel_ptr() { return (const void*)reduce_kernel; }
+const void* slab_sum_kernel_ptr() { return (const void*)slab_sum_kernel; }
 
 void grid_prep(const PrepArgs& a, dim3* grid, dim3* block) {
   *block = dim3(256);
@@ -1047,6 +1122,10 @@ void grid_prep(const PrepArgs& a, dim3* grid, dim3* block) {
 void grid_reduce(const ReduceArgs& a, dim3* grid, dim3* block) {
   *block = dim3(256);
   *grid = dim3((unsigned)((a.sh.P + 255) / 256), (unsigned)a.n_sub);
+}
+void grid_slab_sum(const ReduceArgs& a, dim3* grid, dim3* block) {
+  *block = dim3(256);
+  *grid = dim3((unsigned)((a.sh.slab_floats + 255) / 256), (unsigned)a.n_sub, (unsigned)a.n_chunks);
 }
 
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
@@ -1071,6 +1150,8 @@ hipError_t launch_step(const StepArgs& a, int tile_points, int n_wg, hipStream_t
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   dim3 grid, block;
+  grid_slab_sum(a, &grid, &block);
+  hipLaunchKernelGGL(slab_sum_kernel, grid, block, 0, s, a);
   grid_reduce(a, &grid, &block);
   hipLaunchKernelGGL(reduce_kernel, grid, block, 0, s, a);
   return hipGetLastError();

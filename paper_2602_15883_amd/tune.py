@@ -1,0 +1,126 @@
+"""Autotuner for the fused step's launch shape.
+
+Knobs: collocation points per tile (16, or 32 when the workgroup has at most
+four waves) and persistent workgroups per compute unit.  Each candidate is a
+fresh context over the same device tensors; its fused-kernel time is measured
+with HIP events (PINN_TIME_KERNEL) over a few steps without the Adam update.
+Winners are cached in JSON keyed by (arch, dim, width, depth, subdomain
+count, log2 of the collocation point count).  Lookup order: the user cache
+(DDPINN_TUNE_CACHE or ~/.cache/ddpinn/tune.json), then the table shipped with
+the package (tuned.json), else the library defaults.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+from typing import Dict, List, Optional
+
+import torch
+
+from .context import Context
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SHIPPED = os.path.join(HERE, "tuned.json")
+
+
+def user_cache_path() -> str:
+    return os.environ.get("DDPINN_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "ddpinn", "tune.json"))
+
+
+def arch_name() -> str:
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def tune_key(dim, width, depth, n_sub, n_pde) -> str:
+    b = int(math.floor(math.log2(max(n_pde, 1))))
+    return f"{arch_name()}|d{dim}|w{width}|h{depth}|s{n_sub}|n2^{b}"
+
+
+def _load(path) -> Dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def lookup(key: str) -> Optional[dict]:
+    for path in (user_cache_path(), SHIPPED):
+        e = _load(path).get(key)
+        if e:
+            return e
+    return None
+
+
+def store(key: str, entry: dict, path: Optional[str] = None):
+    path = path or user_cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tab = _load(path)
+    tab[key] = entry
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(tab, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def candidates(width: int) -> List[dict]:
+    waves = (width + 15) // 16
+    out = []
+    for tp in (16, 32):
+        if tp == 32 and waves > 4:
+            continue
+        for bpc in (1, 2, 3, 4):
+            out.append({"tile_points": tp, "blocks_per_cu": bpc})
+    return out
+
+
+def measure(make_ctx, cand: dict, steps: int = 3, warmup: int = 1) -> float:
+    """Average fused-kernel milliseconds of one candidate (no Adam update)."""
+    ctx: Context = make_ctx(**cand)
+    try:
+        info = ctx.launch_info()
+        if info["tile_points"] != cand["tile_points"]:
+            return float("inf")
+        for _ in range(warmup):
+            ctx.step(1, update=False, time_kernel=True)
+        ctx.kernel_time()
+        for _ in range(steps):
+            ctx.step(1, update=False, time_kernel=True)
+        ms, n = ctx.kernel_time()
+        return ms / max(n, 1)
+    finally:
+        ctx.close()
+
+
+def autotune(make_ctx, dim, width, depth, n_sub, n_pde, steps: int = 3,
+             cache: bool = True, force: bool = False, verbose: bool = False) -> dict:
+    """Return the best {tile_points, blocks_per_cu} for this shape, from the
+    caches or by timing every candidate.  make_ctx(**cand) builds a Context."""
+    key = tune_key(dim, width, depth, n_sub, n_pde)
+    if not force:
+        e = lookup(key)
+        if e:
+            return {"tile_points": e["tile_points"], "blocks_per_cu": e["blocks_per_cu"]}
+    best, best_ms, trials = None, float("inf"), []
+    for cand in candidates(width):
+        try:
+            ms = measure(make_ctx, cand, steps=steps)
+        except Exception as ex:  # a candidate the library rejects
+            if verbose:
+                print("tune: skip", cand, ex)
+            continue
+        trials.append({**cand, "ms": ms})
+        if verbose:
+            print("tune:", cand, f"{ms:.3f} ms")
+        if ms < best_ms:
+            best, best_ms = cand, ms
+    if best is None:
+        raise RuntimeError("no launch candidate worked")
+    if cache:
+        store(key, {**best, "ms": best_ms, "trials": trials})
+    return dict(best)
