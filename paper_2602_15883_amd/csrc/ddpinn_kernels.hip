@@ -208,22 +208,33 @@ __device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]
 
 // acc[cb] += A(16 rows of this wave) * B(LDS [16*NCB cols][S], K = Wp)
 template <int NCB>
+__device__ __forceinline__ void mfma_step(const v4f a, const float* bb, int S, int s4, v4f (&acc)[NCB]) {
+  v4f b[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const v4f*>(bb + cb * 16 * S + 4 * s4);
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[q], b[cb][q], acc[cb]);
+}
+
+template <int NCB>
 __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const float* bufB,
                                           int S, int K4, int g, int j, int lane,
                                           v4f (&acc)[NCB]) {
   const float* bb = bufB + j * S + g * (4 * K4);
   const float* ap = afrag + lane * 4;
-  for (int s4 = 0; s4 < K4; ++s4) {
-    const v4f a = ldg4(ap + s4 * 256);
-    v4f b[NCB];
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      b[cb] = *reinterpret_cast<const v4f*>(bb + cb * 16 * S + 4 * s4);
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[q], b[cb][q], acc[cb]);
+  // two weight-fragment registers: the fragment of the next step is in
+  // flight while the MFMAs of the current step run
+  v4f a0 = ldg4(ap);
+  int s4 = 0;
+  for (; s4 + 2 <= K4; s4 += 2) {
+    const v4f a1 = ldg4(ap + (s4 + 1) * 256);
+    mfma_step<NCB>(a0, bb, S, s4, acc);
+    a0 = ldg4(ap + (s4 + 2 < K4 ? s4 + 2 : s4 + 1) * 256);
+    mfma_step<NCB>(a1, bb, S, s4 + 1, acc);
   }
+  if (s4 < K4) mfma_step<NCB>(a0, bb, S, s4, acc);
 }
 
 // dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col], t < NNB
@@ -463,15 +474,18 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     __syncthreads();
 
     v4f acc[NCB];
-    // ---- forward: input layer
+    // ---- forward: input layer.  Activations ping-pong between the two LDS
+    // stacks, so one barrier per layer suffices and each wave's activation
+    // work overlaps the other waves' GEMMs.
+    float* hin = bufH;
+    float* hout = bufG;
     if (pde) input_layer<DIM, NCB, M_PDE>(acc, W1p, bp, xin, w, g, j);
     else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      stg4(stash_w + ((0 * NCB + cb) * 64 + lane) * 4, acc[cb]);
+    for (int cb = 0; cb < NCB; ++cb) stg4(stash_w + ((0 * NCB + cb) * 64 + lane) * 4, acc[cb]);
     if (pde) act_forward<DIM, NCB, M_PDE>(acc);
     else act_forward<DIM, NCB, M_VALUE>(acc);
-    store_fwd<NCB>(bufH, S, acc, w, g, j);
+    store_fwd<NCB>(hin, S, acc, w, g, j);
     __syncthreads();
 
     // ---- forward: hidden layers 2..H
@@ -479,22 +493,23 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
-      gemm_rows<NCB>(Wf, bufH, S, K4, g, j, lane, acc);
+      gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
       if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, g);
       else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
-        stg4(stash_w + (((l - 1) * NCB + cb) * 64 + lane) * 4, acc[cb]);
-      __syncthreads();
+      for (int cb = 0; cb < NCB; ++cb) stg4(stash_w + (((l - 1) * NCB + cb) * 64 + lane) * 4, acc[cb]);
       if (pde) act_forward<DIM, NCB, M_PDE>(acc);
       else act_forward<DIM, NCB, M_VALUE>(acc);
-      store_fwd<NCB>(bufH, S, acc, w, g, j);
+      store_fwd<NCB>(hout, S, acc, w, g, j);
       __syncthreads();
+      float* t = hin;
+      hin = hout;
+      hout = t;
     }
 
-    // ---- output layer
-    if (pde) output_layer<DIM, NCB, M_PDE>(bufH, S, Wp, Wop, bop, ys, tid, nthr);
-    else output_layer<DIM, NCB, M_VALUE>(bufH, S, Wp, Wop, bop, ys, tid, nthr);
+    // ---- output layer (h_H is in hin)
+    if (pde) output_layer<DIM, NCB, M_PDE>(hin, S, Wp, Wop, bop, ys, tid, nthr);
+    else output_layer<DIM, NCB, M_VALUE>(hin, S, Wp, Wop, bop, ys, tid, nthr);
     __syncthreads();
 
     // ---- residuals, losses and output seeds ybar = dL/dy
@@ -598,7 +613,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       if (tid < D * Wp) {
         const int o = tid / Wp, n = tid - o * Wp;
         float s = 0.f;
-        for (int col = 0; col < NCOL; ++col) s += yb[o * NCOL + col] * bufH[col * S + n];
+        for (int col = 0; col < NCOL; ++col) s += yb[o * NCOL + col] * hin[col * S + n];
         dwo += s;
       }
       if (tid < D) {
@@ -621,7 +636,6 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         }
       }
     }
-    __syncthreads();
 
     // ---- hidden and input layer adjoints
     for (int l = H; l >= 1; --l) {
@@ -672,11 +686,14 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         }
         break;
       }
-      store_fwd<NCB>(bufG, S, acc, w, g, j);
-      // recompute h_{l-1} from the stashed z_{l-1}; keep z_{l-1} for the next adjoint
+      // z_{l-1} from the stash (kept for the next adjoint); then wait until
+      // every wave has finished reading the LDS stacks before overwriting them
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
         zs[cb] = ldg4(stash_w + (((l - 2) * NCB + cb) * 64 + lane) * 4);
+      __syncthreads();
+      store_fwd<NCB>(bufG, S, acc, w, g, j);
+      // recompute h_{l-1} from z_{l-1}
       if (pde) act_store_bwd<DIM, NCB, M_PDE>(bufH, S2, zs, w, g, j);
       else act_store_bwd<DIM, NCB, M_VALUE>(bufH, S2, zs, w, g, j);
       __syncthreads();
@@ -710,7 +727,6 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
         gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc);
       }
-      __syncthreads();
     }
 
     // ---- end of segment: write the accumulated gradient pieces and losses
