@@ -14,7 +14,9 @@
  * (section 2.2, final local objective, plus the optional reference-anchor
  * pressure term L_anc; lam_gh_p^space is forced to 0 on master subdomains,
  * section 2.2 decoupled asymmetric weighting), its exact gradient, and one
- * Adam update (Algorithm 1, optimizer step).  L_PDE is the mean squared
+ * Adam update (Algorithm 1, optimizer step), optionally after global-norm
+ * gradient clipping and with a step-decayed learning rate (the 3D cylinder
+ * recipe of section 3.3 and appendix B).  L_PDE is the mean squared
  * incompressible Navier-Stokes residual (section 2.1, residuals r1-r4);
  * every MSE sums over components and divides by the number of points; both
  * ghost pressure parts divide by the subdomain's total ghost count.
@@ -81,7 +83,7 @@ typedef struct {
   int32_t width;          /* W, 1..128                                        */
   int32_t depth;          /* H hidden layers, 1..16                           */
   int32_t n_sub;          /* number of subdomains, 1..4096                    */
-  int32_t activation;     /* 0 = tanh (the only value accepted)               */
+  int32_t activation;     /* 0 = tanh, 1 = sin (the paper's cylinder networks) */
   uint32_t flags;         /* PINN_GRAPH                                       */
   double nu;              /* kinematic viscosity 1/Re                         */
   float lam[6];           /* obs, PDE, gh_u, gh_p^space, gh_p^time, anchor    */
@@ -89,6 +91,13 @@ typedef struct {
   int32_t tile_points;    /* collocation points per tile: 0 = tuned, 16, 32   */
   int32_t blocks_per_cu;  /* persistent workgroups per CU: 0 = occupancy max  */
   int64_t max_query_points; /* largest n accepted by pinn_query (routing)     */
+  float comp_w[3];        /* weights of the velocity components in L_obs and
+                             L_gh_u (section 3.3 uses 1, 5, 100); all zero
+                             means all ones                                   */
+  float clip_norm;        /* clip each subdomain's gradient to this global L2
+                             norm before Adam (section 3.3: 1.0); 0 = off     */
+  float lr_factor;        /* step decay: lr_t = lr * lr_factor^floor((t-1) /  */
+  int32_t lr_interval;    /*   lr_interval) (appendix B); interval 0 = off    */
 } pinn_config;
 
 typedef struct {
@@ -131,7 +140,7 @@ pinn_status pinn_create(const pinn_config *cfg, const pinn_subdomain *subs,
  * theta, adam_m, adam_v.
  *   loss_out: device [n_sub][7] = {L_obs, L_PDE, L_gh_u, L_gh_p^space,
  *             L_gh_p^time, L_anc, L} (terms unweighted, L weighted), or NULL.
- *   grad_out: device [n_sub][P] gradient dL/dtheta, or NULL.
+ *   grad_out: device [n_sub][P] gradient dL/dtheta (before clipping), or NULL.
  * The gradient sum is deterministic: the same inputs give bitwise the same
  * results on the same device and launch configuration.
  */

@@ -69,6 +69,12 @@ def lib():
         L.or_route.argtypes = [_i, _i, _p, _p, _l, _p]
         L.or_query2d.argtypes = [_i, _i, _i, _p, _p, _p, _l, _p]
         L.or_exchange.argtypes = [_i, _i, _i, _p, _i, _p, _p, _l, _p]
+        L.or_set_activation.argtypes = [_i]
+        L.or_set_component_weights.argtypes = [_p]
+        L.or_clip_grad.restype = _d
+        L.or_clip_grad.argtypes = [_p, _l, _d]
+        L.or_step_lr.restype = _d
+        L.or_step_lr.argtypes = [_d, _d, _l, _l]
         _lib = L
     return _lib
 
@@ -198,3 +204,31 @@ def exchange(dim, width, depth, theta_nb, nb_is_master, x_anc, x):
     lib().or_exchange(dim, width, depth, _ptr(th), int(bool(nb_is_master)), _ptr(xa),
                       _ptr(x), x.shape[0], _ptr(out))
     return out
+
+
+ACTIVATIONS = {"tanh": 0, "sin": 1}
+
+
+def set_activation(name: str = "tanh"):
+    """Activation of every network the oracle evaluates from now on."""
+    lib().or_set_activation(ACTIVATIONS[name])
+
+
+def set_component_weights(w=None):
+    """Weights of the velocity components in L_obs and L_gh_u (None: ones)."""
+    if w is None:
+        lib().or_set_component_weights(None)
+    else:
+        a = _f64(list(w) + [1.0] * (3 - len(w)))
+        lib().or_set_component_weights(_ptr(a))
+
+
+def clip_grad(g, c):
+    """Global-norm clipping; returns (clipped copy, norm before clipping)."""
+    gg = _f64(g).copy()
+    nrm = lib().or_clip_grad(_ptr(gg), gg.size, float(c))
+    return gg, float(nrm)
+
+
+def step_lr(lr, factor, interval, t):
+    return float(lib().or_step_lr(float(lr), float(factor), int(interval), int(t)))

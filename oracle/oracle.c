@@ -9,7 +9,8 @@
  * the definitions, written so each line can be checked against the paper.
  *
  * What it computes (paper section 2.1 and 2.2):
- *   - the local expert: a fully connected tanh MLP (x, t) -> (u, p)
+ *   - the local expert: a fully connected tanh (or sin, section 3.2-3.3) MLP
+ *     (x, t) -> (u, p)
  *     (section 2.1, network equation; section 2.2, "local expert"),
  *   - the derivatives the Navier-Stokes residuals need: d/dx_j, d/dt and
  *     d2/dx_j^2 of every output, carried through each layer in forward mode
@@ -21,7 +22,9 @@
  *     objective), plus an optional reference-anchor pressure term L_anc,
  *   - the exact gradient of the weighted loss with respect to every parameter
  *     (hand-derived adjoint of the forward above),
- *   - one Adam update (Algorithm 1, optimizer step),
+ *   - one Adam update (Algorithm 1, optimizer step), with the optional
+ *     global-norm gradient clipping and step learning-rate decay of the 3D
+ *     cylinder recipe (section 3.3, appendix B),
  *   - point queries: routing to the half-open subdomain box and (u, v, p, w)
  *     with vorticity w = v_x - u_y (section 3, stitching of local experts),
  *   - the ghost-target exchange with reference anchor normalisation
@@ -48,13 +51,28 @@
 
 typedef struct {
   int dim, din, dout, W, H;
+  int act;                 /* 0 = tanh, 1 = sin (the paper's cylinder networks) */
   const double *theta;
 } net_t;
 
+static int g_act = 0;      /* activation of the nets built by the entry points */
+
 static void net_init(net_t *n, int dim, int W, int H, const double *theta) {
   n->dim = dim; n->din = dim + 1; n->dout = dim + 1; n->W = W; n->H = H;
+  n->act = g_act;
   n->theta = theta;
 }
+
+/* activation sigma and its first three derivatives at z */
+static void act_derivs(int act, double z, double *s, double *s1, double *s2, double *s3) {
+  if (act == 1) {            /* sin: sin, cos, -sin, -cos */
+    *s = sin(z); *s1 = cos(z); *s2 = -*s; *s3 = -*s1;
+  } else {                   /* tanh: s, 1 - s^2, -2 s (1 - s^2), 2 (1 - s^2)(3 s^2 - 1) */
+    *s = tanh(z); *s1 = 1.0 - *s * *s; *s2 = -2.0 * *s * *s1; *s3 = 2.0 * *s1 * (3.0 * *s * *s - 1.0);
+  }
+}
+
+void or_set_activation(int act) { g_act = act; }
 
 long or_nparams(int dim, int W, int H) {
   long din = dim + 1, dout = dim + 1;
@@ -112,12 +130,11 @@ static void forward_point(const net_t *n, const double *xi, int C,
           zl[c * W + k] = s;
         }
     }
-    /* activation with the chain rule: h = tanh(z0); h_j = tanh'(z0) z_j;
-     * h_jj = tanh''(z0) z_j^2 + tanh'(z0) z_jj */
+    /* activation with the chain rule: h = sigma(z0); h_j = sigma'(z0) z_j;
+     * h_jj = sigma''(z0) z_j^2 + sigma'(z0) z_jj */
     for (int k = 0; k < W; k++) {
-      double s = tanh(zl[k]);
-      double s1 = 1.0 - s * s;
-      double s2 = -2.0 * s * s1;
+      double s, s1, s2, s3;
+      act_derivs(n->act, zl[k], &s, &s1, &s2, &s3);
       hl[k] = s;
       if (C > 1) {
         for (int j = 0; j <= d; j++) hl[(1 + j) * W + k] = s1 * zl[(1 + j) * W + k];
@@ -173,10 +190,8 @@ static void backward_point(const net_t *n, const double *xi, int C,
     const double *zl = z + (long)l * C * W;
     /* activation adjoint (reverse of the chain rule above) */
     for (int k = 0; k < W; k++) {
-      double s = tanh(zl[k]);
-      double s1 = 1.0 - s * s;
-      double s2 = -2.0 * s * s1;
-      double s3 = 2.0 * s1 * (3.0 * s * s - 1.0);
+      double s, s1, s2, s3;
+      act_derivs(n->act, zl[k], &s, &s1, &s2, &s3);
       double z0bar = s1 * hbar[k];
       if (C > 1) {
         for (int j = 0; j <= d; j++) {
@@ -340,6 +355,13 @@ void or_residuals(int dim, double nu, const double *y, long n, double *r) {
  *   Points are processed in static blocks by thread; each thread sums into
  *   its own accumulator and the accumulators are added in thread order.
  */
+/* weights of the velocity components in L_obs and L_gh_u (section 3.3 uses
+ * (1, 5, 100) for (u, v, w)); all ones by default */
+static double g_cw[3] = {1.0, 1.0, 1.0};
+void or_set_component_weights(const double *w) {
+  for (int i = 0; i < 3; i++) g_cw[i] = w ? w[i] : 1.0;
+}
+
 void or_loss_grad(int dim, int W, int H, double nu, const double *lam, int is_master,
                   const double *theta,
                   const double *pde_x, long n_pde,
@@ -393,8 +415,8 @@ void or_loss_grad(int dim, int W, int H, double nu, const double *lam, int is_ma
       for (int o = 0; o < D; o++) yb[o] = 0.0;
       for (int i = 0; i < d; i++) {
         double e = y[i] - obs_u[p * d + i];
-        s += e * e;
-        yb[i] = 2.0 * l_obs * e / (double)n_obs;
+        s += g_cw[i] * e * e;
+        yb[i] = 2.0 * l_obs * g_cw[i] * e / (double)n_obs;
       }
       myl[0] += s;
       if (myg) backward_point(&nt, xi, 1, z, h, yb, myg, hb, zb);
@@ -408,8 +430,8 @@ void or_loss_grad(int dim, int W, int H, double nu, const double *lam, int is_ma
       double s = 0.0;
       for (int i = 0; i < d; i++) {
         double e = y[i] - tgt[i];
-        s += e * e;
-        yb[i] = 2.0 * l_ghu * e / (double)n_gh;
+        s += g_cw[i] * e * e;
+        yb[i] = 2.0 * l_ghu * g_cw[i] * e / (double)n_gh;
       }
       myl[2] += s;
       double ep = y[d] - tgt[d];
@@ -451,6 +473,26 @@ void or_loss_grad(int dim, int W, int H, double nu, const double *lam, int is_ma
     }
   }
   free(tl); free(tg);
+}
+
+/* Gradient clipping by global norm (section 3.3: maximum norm 1.0):
+ * g <- g * min(1, c / ||g||_2).  Returns ||g||_2 before clipping. */
+double or_clip_grad(double *g, long P, double c) {
+  double ss = 0.0;
+  for (long i = 0; i < P; i++) ss += g[i] * g[i];
+  double nrm = sqrt(ss);
+  if (c > 0.0 && nrm > c) {
+    double f = c / nrm;
+    for (long i = 0; i < P; i++) g[i] *= f;
+  }
+  return nrm;
+}
+
+/* Step decay of the learning rate (appendix B, "LR factor & interval"):
+ * lr_t = lr * factor^floor((t - 1) / interval); interval <= 0 keeps lr. */
+double or_step_lr(double lr, double factor, long interval, long t) {
+  if (interval <= 0) return lr;
+  return lr * pow(factor, (double)((t - 1) / interval));
 }
 
 /* Adam with bias correction, step t >= 1 (Algorithm 1 optimizer step). */

@@ -79,6 +79,8 @@ class Context:
                  lam, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
                  eps: float = 1e-8, graph: bool = True, tile_points: int = 0,
                  blocks_per_cu: int = 0, max_query_points: int = 1 << 22,
+                 activation: str = "tanh", comp_w=None, clip_norm: float = 0.0,
+                 lr_factor: float = 1.0, lr_interval: int = 0,
                  device=None, stream=None):
         if not torch.cuda.is_available():
             raise RuntimeError("libddpinn needs a ROCm GPU (gfx950); none is visible")
@@ -90,7 +92,14 @@ class Context:
         self.P = abi.num_params(dim, width, depth)
         cfg = PinnConfig()
         cfg.dim, cfg.width, cfg.depth, cfg.n_sub = dim, width, depth, self.n_sub
-        cfg.activation = 0
+        cfg.activation = {"tanh": 0, "sin": 1}[activation]
+        self.activation = activation
+        if comp_w is not None:
+            for k, v in enumerate(list(comp_w)[:3]):
+                cfg.comp_w[k] = float(v)
+        cfg.clip_norm = float(clip_norm)
+        cfg.lr_factor = float(lr_factor)
+        cfg.lr_interval = int(lr_interval)
         cfg.flags = abi.PINN_GRAPH if graph else 0
         cfg.nu = float(nu)
         for k in range(6):
@@ -229,5 +238,9 @@ def context_from_problem(pb, device="cuda", **kw) -> Context:
     """Build a Context from a host problem description (an object with dim,
     width, depth, nu, lam, lr, beta1, beta2, eps and subs of NumPy arrays)."""
     subs = [subdomain_to_device(s, device) for s in pb.subs]
+    opts = dict(activation=getattr(pb, "activation", "tanh"), comp_w=getattr(pb, "comp_w", None),
+                clip_norm=getattr(pb, "clip_norm", 0.0), lr_factor=getattr(pb, "lr_factor", 1.0),
+                lr_interval=getattr(pb, "lr_interval", 0))
+    opts.update(kw)
     return Context(pb.dim, pb.width, pb.depth, subs, pb.nu, pb.lam, lr=pb.lr, beta1=pb.beta1,
-                   beta2=pb.beta2, eps=pb.eps, device=device, **kw)
+                   beta2=pb.beta2, eps=pb.eps, device=device, **opts)

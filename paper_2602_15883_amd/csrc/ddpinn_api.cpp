@@ -156,7 +156,9 @@ struct pinn_ctx {
   float* d_frag = nullptr;
   float* d_partial = nullptr;
   float* d_loss_ws = nullptr;
-  int32_t* d_flag = nullptr;
+  float* d_gbuf = nullptr;
+  float* d_normpart = nullptr;
+  float* d_clip = nullptr;
   float* d_boxes = nullptr;
   ExchangeItem* d_xitems = nullptr;
   float** d_targets = nullptr;
@@ -168,7 +170,8 @@ struct pinn_ctx {
   // graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  hipGraphNode_t n_reduce = nullptr;
+  hipGraphNode_t n_reduce = nullptr;   // Adam node (t, lr, update change per step)
+  hipGraphNode_t n_grad = nullptr;     // gradient node (output pointers change per step)
   ReduceArgs rargs{};
   StepArgs sargs{};
   PrepArgs pargs{};
@@ -232,7 +235,14 @@ static pinn_status validate(const pinn_config* cfg, const pinn_subdomain* subs) 
   if (cfg->depth < 1) return fail(PINN_E_INVAL, "depth must be >= 1");
   if (cfg->depth > kMaxDepth) return fail(PINN_E_UNSUPPORTED, "depth %d > %d", cfg->depth, kMaxDepth);
   if (cfg->n_sub < 1 || cfg->n_sub > kMaxSub) return fail(PINN_E_INVAL, "n_sub must be in [1, %d]", kMaxSub);
-  if (cfg->activation != 0) return fail(PINN_E_UNSUPPORTED, "only tanh (activation 0) is supported");
+  if (cfg->activation != 0 && cfg->activation != 1)
+    return fail(PINN_E_UNSUPPORTED, "activation must be 0 (tanh) or 1 (sin)");
+  for (int k = 0; k < 3; ++k)
+    if (!(std::isfinite(cfg->comp_w[k]) && cfg->comp_w[k] >= 0)) return fail(PINN_E_INVAL, "comp_w[%d] must be finite and >= 0", k);
+  if (!(std::isfinite(cfg->clip_norm) && cfg->clip_norm >= 0)) return fail(PINN_E_INVAL, "clip_norm must be finite and >= 0");
+  if (cfg->lr_interval < 0) return fail(PINN_E_INVAL, "lr_interval must be >= 0");
+  if (cfg->lr_interval > 0 && !(std::isfinite(cfg->lr_factor) && cfg->lr_factor > 0))
+    return fail(PINN_E_INVAL, "lr_factor must be finite and > 0");
   if (!(std::isfinite(cfg->nu) && cfg->nu >= 0)) return fail(PINN_E_INVAL, "nu must be finite and >= 0");
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(cfg->lam[k])) return fail(PINN_E_INVAL, "lam[%d] not finite", k);
@@ -281,6 +291,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->cfg = *cfg;
   c->n_sub = cfg->n_sub;
   c->sh = make_shape(cfg->dim, cfg->width, cfg->depth);
+  c->sh.act = cfg->activation;
   c->subs.assign(subs, subs + cfg->n_sub);
   const Shape& sh = c->sh;
 
@@ -300,7 +311,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
     // 32-point tiles hold twice the registers: at most 4 waves (Wp <= 64)
     if ((int64_t)lf * 4 > max_lds || (tp == 32 && c->threads > 256)) { *occ = 0; return PINN_OK; }
     int nb = 0;
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel_ptr(sh.dim, tp), c->threads, (size_t)lf * 4));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel_ptr(sh.dim, tp, sh.act), c->threads, (size_t)lf * 4));
     *occ = nb;
     return PINN_OK;
   };
@@ -391,7 +402,10 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   const size_t o_partial = take(sizeof(float) * (size_t)c->n_sub * c->n_chunks * sh.slab_floats);
   const size_t o_frag = take(sizeof(float) * (size_t)c->n_sub * sh.frag_floats);
   const size_t o_loss = take(sizeof(float) * 8 * c->n_sub);
-  const size_t o_flag = take(64);
+  const int n_gblk = (int)((sh.P + 255) / 256);
+  const size_t o_gbuf = take(sizeof(float) * (size_t)c->n_sub * sh.P);
+  const size_t o_normpart = take(sizeof(float) * (size_t)c->n_sub * n_gblk);
+  const size_t o_clip = take(sizeof(float) * c->n_sub);
   const size_t o_boxes = take(sizeof(float) * 8 * c->n_sub);
   const size_t o_xitems = take(sizeof(ExchangeItem) * c->x_cap);
   const size_t o_targets = take(sizeof(float*) * c->n_sub);
@@ -416,7 +430,9 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->d_frag = (float*)(ws + o_frag);
   c->d_partial = (float*)(ws + o_partial);
   c->d_loss_ws = (float*)(ws + o_loss);
-  c->d_flag = (int32_t*)(ws + o_flag);
+  c->d_gbuf = (float*)(ws + o_gbuf);
+  c->d_normpart = (float*)(ws + o_normpart);
+  c->d_clip = (float*)(ws + o_clip);
   c->d_boxes = (float*)(ws + o_boxes);
   c->d_xitems = (ExchangeItem*)(ws + o_xitems);
   c->d_targets = (float**)(ws + o_targets);
@@ -459,6 +475,9 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
       if (q <= cfg->dim) c->gmax[q] = std::max(c->gmax[q], u.hi[q]);
     }
     d.is_master = u.is_master ? 1 : 0;
+    const bool cw_set = cfg->comp_w[0] != 0.f || cfg->comp_w[1] != 0.f || cfg->comp_w[2] != 0.f;
+    for (int q = 0; q < 3; ++q) d.cw[q] = cw_set ? cfg->comp_w[q] : 1.f;
+    d.cw[3] = 0.f;
   }
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemcpyAsync(c->d_subs, sd.data(), sizeof(SubDev) * c->n_sub, hipMemcpyHostToDevice, s));
@@ -490,6 +509,10 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->rargs.partial = c->d_partial;
   c->rargs.n_chunks = c->n_chunks;
   c->rargs.loss_ws = c->d_loss_ws;
+  c->rargs.gbuf = c->d_gbuf;
+  c->rargs.normpart = c->d_normpart;
+  c->rargs.clip_scale = c->d_clip;
+  c->rargs.clip = cfg->clip_norm;
   c->rargs.n_sub = c->n_sub;
   c->rargs.lr = cfg->lr;
   c->rargs.beta1 = cfg->beta1;
@@ -511,7 +534,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
     HIPCHECK(hipGraphAddKernelNode(&n1, gr, nullptr, 0, &kp));
     void* sa[] = {&c->sargs};
     hipKernelNodeParams ks{};
-    ks.func = (void*)step_kernel_ptr(sh.dim, c->tile_points);
+    ks.func = (void*)step_kernel_ptr(sh.dim, c->tile_points, sh.act);
     ks.gridDim = dim3(c->n_wg);
     ks.blockDim = dim3(c->threads);
     ks.sharedMemBytes = (unsigned)(c->lds_floats * 4);
@@ -526,11 +549,31 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
     kq.kernelParams = ra;
     hipGraphNode_t n25;
     HIPCHECK(hipGraphAddKernelNode(&n25, gr, &n2, 1, &kq));
+    hipKernelNodeParams kg{};
+    grid_reduce(c->rargs, &kg.gridDim, &kg.blockDim);
+    kg.func = (void*)grad_kernel_ptr();
+    kg.kernelParams = ra;
+    hipGraphNode_t ng;
+    HIPCHECK(hipGraphAddKernelNode(&ng, gr, &n25, 1, &kg));
+    c->n_grad = ng;
+    hipGraphNode_t last = ng;
+    int nblk = (int)kg.gridDim.x;
+    void* ca[] = {&c->rargs, &nblk};
+    if (cfg->clip_norm > 0.f) {
+      hipKernelNodeParams kc{};
+      kc.gridDim = dim3(c->n_sub);
+      kc.blockDim = dim3(256);
+      kc.func = (void*)clip_kernel_ptr();
+      kc.kernelParams = ca;
+      hipGraphNode_t nc;
+      HIPCHECK(hipGraphAddKernelNode(&nc, gr, &ng, 1, &kc));
+      last = nc;
+    }
     hipKernelNodeParams kr{};
     grid_reduce(c->rargs, &kr.gridDim, &kr.blockDim);
-    kr.func = (void*)reduce_kernel_ptr();
+    kr.func = (void*)adam_kernel_ptr();
     kr.kernelParams = ra;
-    HIPCHECK(hipGraphAddKernelNode(&n3, gr, &n25, 1, &kr));
+    HIPCHECK(hipGraphAddKernelNode(&n3, gr, &last, 1, &kr));
     HIPCHECK(hipGraphAddKernelNode(&n4, gr, &n3, 1, &kp));
     c->graph = gr;
     c->n_reduce = n3;
@@ -585,12 +628,21 @@ pinn_status pinn_step(pinn_ctx* c, int64_t t, uint32_t flags, float* loss_out, f
   c->rargs.update = update ? 1 : 0;
   c->rargs.loss_out = loss_out;
   c->rargs.grad_out = grad_out;
+  // step decay of the learning rate (appendix B): lr * factor^floor((t-1)/interval)
+  c->rargs.lr = c->cfg.lr;
+  if (c->cfg.lr_interval > 0 && t >= 1)
+    c->rargs.lr = (float)((double)c->cfg.lr * std::pow((double)c->cfg.lr_factor, (double)((t - 1) / c->cfg.lr_interval)));
   const bool timed = flags & PINN_TIME_KERNEL;
   if (!per_sub && !timed && c->gexec) {
     void* ra[] = {&c->rargs};
+    hipKernelNodeParams kg{};
+    grid_reduce(c->rargs, &kg.gridDim, &kg.blockDim);
+    kg.func = (void*)grad_kernel_ptr();
+    kg.kernelParams = ra;
+    HIPCHECK(hipGraphExecKernelNodeSetParams(c->gexec, c->n_grad, &kg));
     hipKernelNodeParams kr{};
     grid_reduce(c->rargs, &kr.gridDim, &kr.blockDim);
-    kr.func = (void*)reduce_kernel_ptr();
+    kr.func = (void*)adam_kernel_ptr();
     kr.kernelParams = ra;
     HIPCHECK(hipGraphExecKernelNodeSetParams(c->gexec, c->n_reduce, &kr));
     HIPCHECK(hipGraphLaunch(c->gexec, s));

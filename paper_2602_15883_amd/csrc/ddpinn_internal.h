@@ -30,6 +30,7 @@ struct SubDev {
   float lam[6];           // effective weights: gh_p^space is 0 on masters
   float inv_n[4];         // 1/n_pde, 1/n_obs, 1/n_gh, 1/n_anc (0 if empty)
   float lo[4], hi[4];
+  float cw[4];            // weights of the velocity components in L_obs, L_gh_u
   int32_t is_master;
   int32_t pad_[3];
 };
@@ -52,7 +53,7 @@ struct Item {
 struct Shape {
   int32_t dim, D, W, H, Wp, NW;   // D = dim+1 inputs/outputs; Wp = W padded to 16; NW = Wp/16
   int32_t P;                      // packed parameter count
-  int32_t pad_;
+  int32_t act;                    // activation: 0 tanh, 1 sin
   // fragment buffer (per subdomain)
   int64_t f_hid;   // hidden layer l (2..H): forward A-fragments at f_hid + (l-2)*2*Wp*Wp,
                    // transposed (backward) A-fragments Wp*Wp further
@@ -96,10 +97,15 @@ struct ReduceArgs {
   float* loss_out;          // [n_sub][7] or null
   float* grad_out;          // [n_sub][P] or null
   float* loss_ws;           // [n_sub][8] always written (finite check)
+  float* gbuf;              // [n_sub][P] gradient
+  float* normpart;          // [n_sub][grid blocks] partial sums of g^2
+  float* clip_scale;        // [n_sub] min(1, clip / ||g||)
   int32_t n_sub;
   int32_t update;           // run Adam
   int64_t t;                // Adam step (1-based)
   float lr, beta1, beta2, eps;
+  float clip;               // global-norm clipping threshold (0: off)
+  int32_t pad_;
 };
 
 struct PrepArgs {
@@ -167,13 +173,14 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_route(const RouteArgs& a, hipStream_t s);
 hipError_t launch_query(const QueryArgs& a, int n_wg, hipStream_t s);
 hipError_t launch_exchange(const ExchangeArgs& a, int n_wg, hipStream_t s);
-hipError_t launch_nonfinite_check(const float* loss_ws, int n_sub, int32_t* flag, hipStream_t s);
 
 // Kernel entry points and their LDS needs (for graph nodes and occupancy).
-const void* step_kernel_ptr(int dim, int tile_points);
+const void* step_kernel_ptr(int dim, int tile_points, int act);
 const void* prep_kernel_ptr();
-const void* reduce_kernel_ptr();
 const void* slab_sum_kernel_ptr();
+const void* grad_kernel_ptr();
+const void* clip_kernel_ptr();
+const void* adam_kernel_ptr();
 void grid_slab_sum(const ReduceArgs& a, dim3* grid, dim3* block);
 int step_lds_floats(const Shape& sh, int tile_points);
 int query_lds_floats(const Shape& sh);

@@ -56,6 +56,9 @@ __device__ __forceinline__ float ldg(const float* p) { return *(const GLOBAL_AS 
 __device__ __forceinline__ void stg4(float* p, v4f v) { *(GLOBAL_AS v4f*)p = v; }
 __device__ __forceinline__ void stg(float* p, float v) { *(GLOBAL_AS float*)p = v; }
 
+// sin and cos with full range reduction (device library)
+__device__ __forceinline__ void sincos_f32(float z, float& s, float& c) { sincosf(z, &s, &c); }
+
 // tanh without branches, from two textbook forms:
 //   |x| < 0.4 : x * P(x^2), P = Maclaurin series of tanh(x)/x through the x^12
 //               term (the first omitted term is below 4e-9 relative)
@@ -78,6 +81,36 @@ __device__ __forceinline__ float tanh_f32(float x) {
   return a < 0.4f ? small : big;
 }
 
+enum : int { ACT_TANH = 0, ACT_SIN = 1 };
+
+// activation sigma(z) and its first derivatives: tanh (section 2.1 networks)
+// or sin (the paper's cylinder networks, section 3.2-3.3)
+template <int ACT>
+__device__ __forceinline__ void act_d2(float z, float& s, float& s1, float& s2) {
+  if constexpr (ACT == ACT_SIN) {
+    sincos_f32(z, s, s1);
+    s2 = -s;
+  } else {
+    s = tanh_f32(z);
+    s1 = 1.f - s * s;
+    s2 = -2.f * s * s1;
+  }
+}
+
+template <int ACT>
+__device__ __forceinline__ void act_d3(float z, float& s, float& s1, float& s2, float& s3) {
+  if constexpr (ACT == ACT_SIN) {
+    sincos_f32(z, s, s1);
+    s2 = -s;
+    s3 = -s1;
+  } else {
+    s = tanh_f32(z);
+    s1 = 1.f - s * s;
+    s2 = -2.f * s * s1;
+    s3 = 2.f * s1 * (3.f * s * s - 1.f);
+  }
+}
+
 // Channel layout of a tile in a given mode.
 //   M_PDE  : CM = 2d+2 channels: 0 value, 1..d d/dx_j, d+1 d/dt, d+2..2d+1 d2/dx_j^2
 //   M_GRAD : CM = d+1 channels: 0 value, 1..d d/dx_j
@@ -94,10 +127,10 @@ struct ModeCfg {
 
 // ---------------------------------------------------------------------------
 // activation: z -> h with the chain rule, in place on accumulator fragments
-//   h = tanh(z0); h_j = s1 z_j; h_jj = s2 z_j^2 + s1 z_jj
-//   s1 = 1 - tanh^2, s2 = -2 tanh s1
+//   h = sigma(z0); h_j = s1 z_j; h_jj = s2 z_j^2 + s1 z_jj
+//   s1, s2 = first and second derivative of sigma at z0
 // ---------------------------------------------------------------------------
-template <int DIM, int NCB, int MODE>
+template <int DIM, int NCB, int MODE, int ACT>
 __device__ __forceinline__ void act_forward(v4f (&a)[NCB]) {
   using M = ModeCfg<DIM, NCB, MODE>;
   constexpr int NPB = M::NPB;
@@ -105,10 +138,9 @@ __device__ __forceinline__ void act_forward(v4f (&a)[NCB]) {
   for (int pb = 0; pb < NPB; ++pb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float s = tanh_f32(a[pb][i]);
-      const float s1 = 1.f - s * s;
+      float s, s1, s2;
+      act_d2<ACT>(a[pb][i], s, s1, s2);
       if constexpr (MODE == M_PDE) {
-        const float s2 = -2.f * s * s1;
 #pragma unroll
         for (int jj = 0; jj < DIM; ++jj) {
           const float z1 = a[(1 + jj) * NPB + pb][i];
@@ -128,7 +160,7 @@ __device__ __forceinline__ void act_forward(v4f (&a)[NCB]) {
 
 // h = act(z) of a stashed pre-activation stack, written straight into the
 // neuron-major LDS layout [neuron][column] (stride S2) used by the dW GEMM.
-template <int DIM, int NCB, int MODE>
+template <int DIM, int NCB, int MODE, int ACT>
 __device__ __forceinline__ void act_store_bwd(float* buf, int S2, const v4f (&z)[NCB], int w, int g, int j) {
   using M = ModeCfg<DIM, NCB, MODE>;
   constexpr int NPB = M::NPB;
@@ -137,11 +169,10 @@ __device__ __forceinline__ void act_store_bwd(float* buf, int S2, const v4f (&z)
     float* row = buf + (16 * w + 4 * g + i) * S2 + j;
 #pragma unroll
     for (int pb = 0; pb < NPB; ++pb) {
-      const float s = tanh_f32(z[pb][i]);
-      const float s1 = 1.f - s * s;
+      float s, s1, s2;
+      act_d2<ACT>(z[pb][i], s, s1, s2);
       row[16 * pb] = s;
       if constexpr (MODE == M_PDE) {
-        const float s2 = -2.f * s * s1;
 #pragma unroll
         for (int jj = 0; jj <= DIM; ++jj) row[16 * ((1 + jj) * NPB + pb)] = s1 * z[(1 + jj) * NPB + pb][i];
 #pragma unroll
@@ -158,8 +189,8 @@ __device__ __forceinline__ void act_store_bwd(float* buf, int S2, const v4f (&z)
 //   zbar_jj = s1 hbar_jj
 //   zbar_j  = s1 hbar_j + 2 s2 z_j hbar_jj      (spatial j; time: s1 hbar_t)
 //   zbar_0  = s1 hbar_0 + s2 sum_j z_j hbar_j + sum_j (s3 z_j^2 + s2 z_jj) hbar_jj
-//   s3 = 2 s1 (3 tanh^2 - 1)
-template <int DIM, int NCB, int MODE>
+//   with s1, s2, s3 the first three derivatives of the activation at z_0
+template <int DIM, int NCB, int MODE, int ACT>
 __device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]) {
   using M = ModeCfg<DIM, NCB, MODE>;
   constexpr int NPB = M::NPB;
@@ -167,11 +198,9 @@ __device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]
   for (int pb = 0; pb < NPB; ++pb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const float s = tanh_f32(zs[pb][i]);
-      const float s1 = 1.f - s * s;
       if constexpr (MODE == M_PDE) {
-        const float s2 = -2.f * s * s1;
-        const float s3 = 2.f * s1 * (3.f * s * s - 1.f);
+        float s, s1, s2, s3;
+        act_d3<ACT>(zs[pb][i], s, s1, s2, s3);
         float z0b = s1 * hb[pb][i];
 #pragma unroll
         for (int jj = 0; jj <= DIM; ++jj) {
@@ -191,6 +220,8 @@ __device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]
         }
         hb[pb][i] = z0b;
       } else {
+        float s, s1, s2;
+        act_d2<ACT>(zs[pb][i], s, s1, s2);
         hb[pb][i] *= s1;
       }
     }
@@ -398,7 +429,7 @@ __host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB) {
 // ---------------------------------------------------------------------------
 // Fused step kernel: persistent over this workgroup's item range.
 // ---------------------------------------------------------------------------
-template <int DIM, int PBP>
+template <int DIM, int PBP, int ACT>
 __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepArgs args) {
   constexpr int D = DIM + 1;
   constexpr int CF = 2 * DIM + 2;
@@ -483,8 +514,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) stg4(stash_w + ((0 * NCB + cb) * 64 + lane) * 4, acc[cb]);
-    if (pde) act_forward<DIM, NCB, M_PDE>(acc);
-    else act_forward<DIM, NCB, M_VALUE>(acc);
+    if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
+    else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
     store_fwd<NCB>(hin, S, acc, w, g, j);
     __syncthreads();
 
@@ -498,8 +529,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) stg4(stash_w + (((l - 1) * NCB + cb) * 64 + lane) * 4, acc[cb]);
-      if (pde) act_forward<DIM, NCB, M_PDE>(acc);
-      else act_forward<DIM, NCB, M_VALUE>(acc);
+      if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
+      else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
       store_fwd<NCB>(hout, S, acc, w, g, j);
       __syncthreads();
       float* t = hin;
@@ -568,8 +599,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
 #pragma unroll
             for (int i = 0; i < DIM; ++i) {
               const float d0 = y[i] - ldg(sd.obs_u + (size_t)idx * DIM + i);
-              sq += d0 * d0;
-              e[i] = 2.f * sd.lam[0] * sd.inv_n[1] * d0;
+              sq += sd.cw[i] * d0 * d0;
+              e[i] = 2.f * sd.lam[0] * sd.inv_n[1] * sd.cw[i] * d0;
             }
             lacc[0] += sq;
           } else if ((idx -= sd.n_obs) < sd.n_gh) {
@@ -578,8 +609,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
 #pragma unroll
             for (int i = 0; i < DIM; ++i) {
               const float d0 = y[i] - tg[i];
-              sq += d0 * d0;
-              e[i] = 2.f * sd.lam[2] * sd.inv_n[2] * d0;
+              sq += sd.cw[i] * d0 * d0;
+              e[i] = 2.f * sd.lam[2] * sd.inv_n[2] * sd.cw[i] * d0;
             }
             lacc[2] += sq;
             const float dp = y[DIM] - tg[DIM];
@@ -639,8 +670,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
 
     // ---- hidden and input layer adjoints
     for (int l = H; l >= 1; --l) {
-      if (pde) act_adjoint<DIM, NCB, M_PDE>(acc, zs);
-      else act_adjoint<DIM, NCB, M_VALUE>(acc, zs);
+      if (pde) act_adjoint<DIM, NCB, M_PDE, ACT>(acc, zs);
+      else act_adjoint<DIM, NCB, M_VALUE, ACT>(acc, zs);
       // db_l: value-channel columns
       {
         const int npb = pde ? MP::NPB : MV::NPB;
@@ -694,8 +725,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       __syncthreads();
       store_fwd<NCB>(bufG, S, acc, w, g, j);
       // recompute h_{l-1} from z_{l-1}
-      if (pde) act_store_bwd<DIM, NCB, M_PDE>(bufH, S2, zs, w, g, j);
-      else act_store_bwd<DIM, NCB, M_VALUE>(bufH, S2, zs, w, g, j);
+      if (pde) act_store_bwd<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w, g, j);
+      else act_store_bwd<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w, g, j);
       __syncthreads();
       // dW_l += Zbar_l H_{l-1}^T into this segment's slab; the slab's current
       // values are requested before each chunk's GEMM so the read overlaps it
@@ -844,8 +875,9 @@ __global__ void slab_sum_kernel(const ReduceArgs a) {
   a.partial[((size_t)s * a.n_chunks + c) * sh.slab_floats + pos] = acc;
 }
 
-// stage 2: gradient of every parameter (partials in chunk order), Adam, losses
-__global__ void reduce_kernel(const ReduceArgs a) {
+// stage 2: gradient of every parameter (partials in chunk order), its
+// per-block sum of squares (for clipping), and the losses
+__global__ void grad_kernel(const ReduceArgs a) {
   const Shape& sh = a.sh;
   const int s = blockIdx.y;
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -853,22 +885,21 @@ __global__ void reduce_kernel(const ReduceArgs a) {
   const int nc = (nseg + kSlabChunk - 1) / kSlabChunk;
   const float* part = a.partial + (size_t)s * a.n_chunks * sh.slab_floats;
   const SubDev& sd = a.subs[s];
+  __shared__ float red[256];
+  float g = 0.f;
   if (p < sh.P) {
     const int64_t pos = slab_pos(sh, p);
-    float g = 0.f;
     for (int c = 0; c < nc; ++c) g += part[(size_t)c * sh.slab_floats + pos];
+    a.gbuf[(size_t)s * sh.P + p] = g;
     if (a.grad_out) a.grad_out[(size_t)s * sh.P + p] = g;
-    if (a.update) {
-      const float m = a.beta1 * sd.m[p] + (1.f - a.beta1) * g;
-      const float v = a.beta2 * sd.v[p] + (1.f - a.beta2) * g * g;
-      sd.m[p] = m;
-      sd.v[p] = v;
-      const float c1 = 1.f - powf(a.beta1, (float)a.t);
-      const float c2 = 1.f - powf(a.beta2, (float)a.t);
-      float* th = const_cast<float*>(sd.theta);
-      th[p] = th[p] - a.lr * (m / c1) / (sqrtf(v / c2) + a.eps);
-    }
   }
+  red[threadIdx.x] = g * g;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.normpart[(size_t)s * gridDim.x + blockIdx.x] = red[0];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     float L[7];
     for (int q = 0; q < 6; ++q) {
@@ -890,6 +921,43 @@ __global__ void reduce_kernel(const ReduceArgs a) {
     }
     a.loss_ws[s * 8 + 7] = 0.f;
   }
+}
+
+// global-norm clipping factor of each subdomain: min(1, c / ||g||), block
+// sums added in a fixed order
+__global__ void clip_kernel(const ReduceArgs a, int nblk) {
+  const int s = blockIdx.x;
+  __shared__ float red[256];
+  float v = 0.f;
+  for (int k = threadIdx.x; k < nblk; k += blockDim.x) v += a.normpart[(size_t)s * nblk + k];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float nrm = sqrtf(red[0]);
+    a.clip_scale[s] = (a.clip > 0.f && nrm > a.clip) ? a.clip / nrm : 1.f;
+  }
+}
+
+// stage 3: Adam on the (clipped) gradient, in place on theta, m, v
+__global__ void adam_kernel(const ReduceArgs a) {
+  const Shape& sh = a.sh;
+  const int s = blockIdx.y;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (!a.update || p >= sh.P) return;
+  const SubDev& sd = a.subs[s];
+  const float g = a.gbuf[(size_t)s * sh.P + p] * (a.clip > 0.f ? a.clip_scale[s] : 1.f);
+  const float m = a.beta1 * sd.m[p] + (1.f - a.beta1) * g;
+  const float v = a.beta2 * sd.v[p] + (1.f - a.beta2) * g * g;
+  sd.m[p] = m;
+  sd.v[p] = v;
+  const float c1 = 1.f - powf(a.beta1, (float)a.t);
+  const float c2 = 1.f - powf(a.beta2, (float)a.t);
+  float* th = const_cast<float*>(sd.theta);
+  th[p] = th[p] - a.lr * (m / c1) / (sqrtf(v / c2) + a.eps);
 }
 
 // ---------------------------------------------------------------------------
@@ -953,7 +1021,7 @@ __host__ __device__ inline QueryLds query_lds(int D, int Wp, int NCB) {
 }
 
 // forward of one staged tile (points in xin) through all layers; output in ys
-template <int DIM, int NCB, int MODE>
+template <int DIM, int NCB, int MODE, int ACT>
 __device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, float* bufH, float* ys,
                                              const float* xin, int S, int tid, int nthr, int w, int g,
                                              int j, int lane) {
@@ -961,7 +1029,7 @@ __device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, f
   const int Wp = sh.Wp, H = sh.H, K4 = Wp / 16;
   v4f acc[NCB];
   input_layer<DIM, NCB, MODE>(acc, fr + sh.f_w1, fr + sh.f_b, xin, w, g, j);
-  act_forward<DIM, NCB, MODE>(acc);
+  act_forward<DIM, NCB, MODE, ACT>(acc);
   store_fwd<NCB>(bufH, S, acc, w, g, j);
   __syncthreads();
   for (int l = 2; l <= H; ++l) {
@@ -971,7 +1039,7 @@ __device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, f
     gemm_rows<NCB>(Wf, bufH, S, K4, g, j, lane, acc);
     add_bias<NCB, M::NPB>(acc, fr + sh.f_b + (l - 1) * Wp, w, g);
     __syncthreads();
-    act_forward<DIM, NCB, MODE>(acc);
+    act_forward<DIM, NCB, MODE, ACT>(acc);
     store_fwd<NCB>(bufH, S, acc, w, g, j);
     __syncthreads();
   }
@@ -979,7 +1047,7 @@ __device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, f
   __syncthreads();
 }
 
-template <int DIM, int MODE>
+template <int DIM, int MODE, int ACT>
 __global__ __launch_bounds__(512) void query_kernel(const QueryArgs a) {
   constexpr int D = DIM + 1, CF = 2 * DIM + 2, NCB = CF;
   using M = ModeCfg<DIM, NCB, MODE>;
@@ -1023,7 +1091,7 @@ __global__ __launch_bounds__(512) void query_kernel(const QueryArgs a) {
       xin[k] = v;
     }
     __syncthreads();
-    forward_tile<DIM, NCB, MODE>(sh, a.subs[sub].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
+    forward_tile<DIM, NCB, MODE, ACT>(sh, a.subs[sub].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
     for (int k = tid; k < NPTS; k += nthr) {
       if (pidx[k] < 0) continue;
       const int64_t q = pidx[k];
@@ -1057,7 +1125,7 @@ __global__ __launch_bounds__(512) void query_kernel(const QueryArgs a) {
 // ---------------------------------------------------------------------------
 // exchange: neighbour values at ghost points, anchor-normalised pressure
 // ---------------------------------------------------------------------------
-template <int DIM>
+template <int DIM, int ACT>
 __global__ __launch_bounds__(512) void exchange_kernel(const ExchangeArgs a) {
   constexpr int D = DIM + 1, CF = 2 * DIM + 2, NCB = CF, NCOL = 16 * NCB;
   extern __shared__ float lds[];
@@ -1087,7 +1155,7 @@ __global__ __launch_bounds__(512) void exchange_kernel(const ExchangeArgs a) {
       xin[k] = v;
     }
     __syncthreads();
-    forward_tile<DIM, NCB, M_VALUE>(sh, a.subs[it.b].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
+    forward_tile<DIM, NCB, M_VALUE, ACT>(sh, a.subs[it.b].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
     float* tg = a.targets[it.a];
     for (int k = tid; k < it.count; k += nthr) {
       for (int o = 0; o < D; ++o) {
@@ -1098,13 +1166,6 @@ __global__ __launch_bounds__(512) void exchange_kernel(const ExchangeArgs a) {
     }
     __syncthreads();
   }
-}
-
-__global__ void nonfinite_kernel(const float* loss_ws, int n_sub, int32_t* flag) {
-  int bad = 0;
-  for (int k = threadIdx.x; k < n_sub * 8; k += blockDim.x)
-    if (!isfinite(loss_ws[k])) bad = 1;
-  if (bad) atomicOr(flag, 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -1123,13 +1184,19 @@ int query_lds_floats(const Shape& sh) {
   return query_lds(sh.D, sh.Wp, 2 * sh.dim + 2).total;
 }
 
-const void* step_kernel_ptr(int dim, int tile_points) {
-  if (dim == 2) return tile_points == 32 ? (const void*)step_kernel<2, 2> : (const void*)step_kernel<2, 1>;
-  return tile_points == 32 ? (const void*)step_kernel<3, 2> : (const void*)step_kernel<3, 1>;
+template <int DIM, int PBP>
+static const void* step_ptr_act(int act) {
+  return act == ACT_SIN ? (const void*)step_kernel<DIM, PBP, ACT_SIN> : (const void*)step_kernel<DIM, PBP, ACT_TANH>;
+}
+const void* step_kernel_ptr(int dim, int tile_points, int act) {
+  if (dim == 2) return tile_points == 32 ? step_ptr_act<2, 2>(act) : step_ptr_act<2, 1>(act);
+  return tile_points == 32 ? step_ptr_act<3, 2>(act) : step_ptr_act<3, 1>(act);
 }
 const void* prep_kernel_ptr() { return (const void*)prep_kernel; }
-const void* reduce_kernel_ptr() { return (const void*)reduce_kernel; }
 const void* slab_sum_kernel_ptr() { return (const void*)slab_sum_kernel; }
+const void* grad_kernel_ptr() { return (const void*)grad_kernel; }
+const void* clip_kernel_ptr() { return (const void*)clip_kernel; }
+const void* adam_kernel_ptr() { return (const void*)adam_kernel; }
 
 void grid_prep(const PrepArgs& a, dim3* grid, dim3* block) {
   *block = dim3(256);
@@ -1154,14 +1221,8 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
 hipError_t launch_step(const StepArgs& a, int tile_points, int n_wg, hipStream_t s) {
   const size_t lds = (size_t)a.lds_floats * sizeof(float);
   const dim3 block(a.sh.NW * 64);
-  if (a.sh.dim == 2) {
-    if (tile_points == 32) hipLaunchKernelGGL((step_kernel<2, 2>), dim3(n_wg), block, lds, s, a);
-    else hipLaunchKernelGGL((step_kernel<2, 1>), dim3(n_wg), block, lds, s, a);
-  } else {
-    if (tile_points == 32) hipLaunchKernelGGL((step_kernel<3, 2>), dim3(n_wg), block, lds, s, a);
-    else hipLaunchKernelGGL((step_kernel<3, 1>), dim3(n_wg), block, lds, s, a);
-  }
-  return hipGetLastError();
+  void* args[] = {const_cast<StepArgs*>(&a)};
+  return hipLaunchKernel(step_kernel_ptr(a.sh.dim, tile_points, a.sh.act), dim3(n_wg), block, args, lds, s);
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
@@ -1169,7 +1230,9 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   grid_slab_sum(a, &grid, &block);
   hipLaunchKernelGGL(slab_sum_kernel, grid, block, 0, s, a);
   grid_reduce(a, &grid, &block);
-  hipLaunchKernelGGL(reduce_kernel, grid, block, 0, s, a);
+  hipLaunchKernelGGL(grad_kernel, grid, block, 0, s, a);
+  if (a.clip > 0.f) hipLaunchKernelGGL(clip_kernel, dim3(a.n_sub), dim3(256), 0, s, a, (int)grid.x);
+  hipLaunchKernelGGL(adam_kernel, grid, block, 0, s, a);
   return hipGetLastError();
 }
 
@@ -1182,44 +1245,48 @@ hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int DIM, int MODE>
+static const void* query_ptr_act(int act) {
+  return act == ACT_SIN ? (const void*)query_kernel<DIM, MODE, ACT_SIN> : (const void*)query_kernel<DIM, MODE, ACT_TANH>;
+}
+
 hipError_t launch_query(const QueryArgs& a, int n_wg, hipStream_t s) {
   const size_t lds = (size_t)a.lds_floats * sizeof(float);
   const dim3 block(a.sh.NW * 64);
   const int mode = (a.what == Q_VALUE) ? M_VALUE : (a.what == Q_UVPW ? M_GRAD : M_PDE);
-  if (a.sh.dim == 2) {
-    if (mode == M_VALUE) hipLaunchKernelGGL((query_kernel<2, M_VALUE>), dim3(n_wg), block, lds, s, a);
-    else if (mode == M_GRAD) hipLaunchKernelGGL((query_kernel<2, M_GRAD>), dim3(n_wg), block, lds, s, a);
-    else hipLaunchKernelGGL((query_kernel<2, M_PDE>), dim3(n_wg), block, lds, s, a);
-  } else {
-    if (mode == M_VALUE) hipLaunchKernelGGL((query_kernel<3, M_VALUE>), dim3(n_wg), block, lds, s, a);
-    else if (mode == M_GRAD) hipLaunchKernelGGL((query_kernel<3, M_GRAD>), dim3(n_wg), block, lds, s, a);
-    else hipLaunchKernelGGL((query_kernel<3, M_PDE>), dim3(n_wg), block, lds, s, a);
-  }
-  return hipGetLastError();
+  const int act = a.sh.act;
+  const void* k;
+  if (a.sh.dim == 2)
+    k = mode == M_VALUE ? query_ptr_act<2, M_VALUE>(act) : (mode == M_GRAD ? query_ptr_act<2, M_GRAD>(act) : query_ptr_act<2, M_PDE>(act));
+  else
+    k = mode == M_VALUE ? query_ptr_act<3, M_VALUE>(act) : (mode == M_GRAD ? query_ptr_act<3, M_GRAD>(act) : query_ptr_act<3, M_PDE>(act));
+  void* args[] = {const_cast<QueryArgs*>(&a)};
+  return hipLaunchKernel(k, dim3(n_wg), block, args, lds, s);
 }
 
 hipError_t launch_exchange(const ExchangeArgs& a, int n_wg, hipStream_t s) {
   const size_t lds = (size_t)a.lds_floats * sizeof(float);
   const dim3 block(a.sh.NW * 64);
-  if (a.sh.dim == 2) hipLaunchKernelGGL((exchange_kernel<2>), dim3(n_wg), block, lds, s, a);
-  else hipLaunchKernelGGL((exchange_kernel<3>), dim3(n_wg), block, lds, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_nonfinite_check(const float* loss_ws, int n_sub, int32_t* flag, hipStream_t s) {
-  hipLaunchKernelGGL(nonfinite_kernel, dim3(1), dim3(256), 0, s, loss_ws, n_sub, flag);
-  return hipGetLastError();
+  const void* k;
+  if (a.sh.dim == 2) k = a.sh.act == ACT_SIN ? (const void*)exchange_kernel<2, ACT_SIN> : (const void*)exchange_kernel<2, ACT_TANH>;
+  else k = a.sh.act == ACT_SIN ? (const void*)exchange_kernel<3, ACT_SIN> : (const void*)exchange_kernel<3, ACT_TANH>;
+  void* args[] = {const_cast<ExchangeArgs*>(&a)};
+  return hipLaunchKernel(k, dim3(n_wg), block, args, lds, s);
 }
 
 // LDS above 64 KiB must be allowed per kernel before launch.
 hipError_t set_lds_limits(int bytes) {
   hipError_t e = hipSuccess;
-  const void* ks[] = {(const void*)step_kernel<2, 1>, (const void*)step_kernel<2, 2>,
-                      (const void*)step_kernel<3, 1>, (const void*)step_kernel<3, 2>,
-                      (const void*)query_kernel<2, M_VALUE>, (const void*)query_kernel<2, M_GRAD>,
-                      (const void*)query_kernel<2, M_PDE>, (const void*)query_kernel<3, M_VALUE>,
-                      (const void*)query_kernel<3, M_GRAD>, (const void*)query_kernel<3, M_PDE>,
-                      (const void*)exchange_kernel<2>, (const void*)exchange_kernel<3>};
+  const void* ks[] = {
+      step_kernel_ptr(2, 16, ACT_TANH), step_kernel_ptr(2, 32, ACT_TANH), step_kernel_ptr(3, 16, ACT_TANH),
+      step_kernel_ptr(3, 32, ACT_TANH), step_kernel_ptr(2, 16, ACT_SIN), step_kernel_ptr(2, 32, ACT_SIN),
+      step_kernel_ptr(3, 16, ACT_SIN), step_kernel_ptr(3, 32, ACT_SIN),
+      query_ptr_act<2, M_VALUE>(ACT_TANH), query_ptr_act<2, M_GRAD>(ACT_TANH), query_ptr_act<2, M_PDE>(ACT_TANH),
+      query_ptr_act<3, M_VALUE>(ACT_TANH), query_ptr_act<3, M_GRAD>(ACT_TANH), query_ptr_act<3, M_PDE>(ACT_TANH),
+      query_ptr_act<2, M_VALUE>(ACT_SIN), query_ptr_act<2, M_GRAD>(ACT_SIN), query_ptr_act<2, M_PDE>(ACT_SIN),
+      query_ptr_act<3, M_VALUE>(ACT_SIN), query_ptr_act<3, M_GRAD>(ACT_SIN), query_ptr_act<3, M_PDE>(ACT_SIN),
+      (const void*)exchange_kernel<2, ACT_TANH>, (const void*)exchange_kernel<3, ACT_TANH>,
+      (const void*)exchange_kernel<2, ACT_SIN>, (const void*)exchange_kernel<3, ACT_SIN>};
   for (const void* k : ks) {
     hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (r != hipSuccess) e = r;

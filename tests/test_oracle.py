@@ -406,3 +406,124 @@ def test_pde_loss_is_mean_of_squared_residuals(orc, dim):
     r = orc.residuals(dim, pb.nu, orc.channels(dim, 6, 2, s.theta, s.pde_x))
     assert L[1] == pytest.approx(np.mean(np.sum(r * r, 1)), rel=1e-13)
     assert L[1] > 1e-3
+
+
+# ------------------------------------------- sine activation, 3D recipe
+@pytest.fixture
+def sin_act(orc):
+    orc.set_activation("sin")
+    yield orc
+    orc.set_activation("tanh")
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_sine_one_hidden_layer_closed_form(sin_act, dim):
+    """H = 1 with sin: u = sum c sin(w.xi + b) + e, u_j = sum c cos(.) w_j,
+    u_jj = -sum c sin(.) w_j^2."""
+    orc = sin_act
+    W, D = 6, dim + 1
+    rng = np.random.default_rng(8)
+    W1, b1 = rng.standard_normal((W, D)), rng.standard_normal(W)
+    C2, e = rng.standard_normal((D, W)), rng.standard_normal(D)
+    theta = np.concatenate([W1.ravel(), b1, C2.ravel(), e])
+    x = rng.uniform(-1, 1, size=(7, D))
+    y = orc.channels(dim, W, 1, theta, x)
+    z = x @ W1.T + b1
+    np.testing.assert_allclose(y[:, 0, :], np.sin(z) @ C2.T + e, rtol=1e-13, atol=1e-13)
+    for j in range(D):
+        np.testing.assert_allclose(y[:, 1 + j, :], (np.cos(z) * W1[:, j]) @ C2.T, rtol=1e-12, atol=1e-13)
+    for j in range(dim):
+        np.testing.assert_allclose(y[:, dim + 2 + j, :], (-np.sin(z) * W1[:, j] ** 2) @ C2.T,
+                                   rtol=1e-12, atol=1e-13)
+
+
+@pytest.mark.parametrize("dim,W,H", TINY_NETS[:2])
+def test_sine_channels_and_gradient_match_finite_differences(sin_act, dim, W, H):
+    orc = sin_act
+    D = dim + 1
+    th = rand_theta(dim, W, H, 20 + dim)
+    x = np.random.default_rng(2).uniform(-0.8, 0.8, size=(5, D))
+    y = orc.channels(dim, W, H, th, x)
+    f = lambda pts: orc.values(dim, W, H, th, pts)
+    for j in range(D):
+        e = np.zeros(D)
+        e[j] = 1.0
+        fd1 = (f(x + 1e-5 * e) - f(x - 1e-5 * e)) / 2e-5
+        assert rel_err(y[:, 1 + j, :], fd1) < 1e-6
+        if j < dim:
+            fd2 = (f(x + 1e-4 * e) - 2 * f(x) + f(x - 1e-4 * e)) / 1e-8
+            assert rel_err(y[:, dim + 2 + j, :], fd2) < 1e-5
+    pb = wl.tiny(dim=dim, width=W, depth=H, seed=31)
+    a = problem_arrays(pb)
+    t0 = pb.subs[0].theta.astype(np.float64)
+    _, g = orc.loss_grad(dim, W, H, pb.nu, pb.lam, t0, **a)
+    fd = np.zeros_like(t0)
+    for i in range(t0.size):
+        tp, tm = t0.copy(), t0.copy()
+        tp[i] += 1e-6
+        tm[i] -= 1e-6
+        fd[i] = (orc.loss_grad(dim, W, H, pb.nu, pb.lam, tp, want_grad=False, **a)[0][6]
+                 - orc.loss_grad(dim, W, H, pb.nu, pb.lam, tm, want_grad=False, **a)[0][6]) / 2e-6
+    assert rel_err(g, fd) < 1e-6
+
+
+def test_component_weights_by_hand(orc):
+    """Weighted velocity components in L_obs and L_gh_u (section 3.3): with a
+    constant network each term is a plain weighted mean of squares."""
+    dim = 3
+    pb = wl.tiny(dim=dim, width=4, depth=2, n_pde=3, n_obs=6, n_gh=5, n_anc=0)
+    s = pb.subs[0]
+    th = np.zeros(pb.n_params)
+    b = np.array([0.2, -0.4, 0.7, 0.1])
+    th[-4:] = b
+    w = np.array([1.0, 5.0, 100.0])
+    orc.set_component_weights(w)
+    try:
+        L, g = orc.loss_grad(dim, 4, 2, pb.nu, pb.lam, th, **problem_arrays(pb))
+        La, ga = orc.loss_grad(dim, 4, 2, pb.nu, pb.lam, th + 0.01, **problem_arrays(pb))
+    finally:
+        orc.set_component_weights(None)
+    L_obs = np.mean(np.sum(w * (b[:3] - s.obs_u.astype(np.float64)) ** 2, 1))
+    L_ghu = np.mean(np.sum(w * (b[:3] - s.gh_up[:, :3].astype(np.float64)) ** 2, 1))
+    assert L[0] == pytest.approx(L_obs, rel=1e-13)
+    assert L[2] == pytest.approx(L_ghu, rel=1e-13)
+    # the pressure terms are untouched by the velocity weights
+    L1, _ = orc.loss_grad(dim, 4, 2, pb.nu, pb.lam, th, **problem_arrays(pb))
+    np.testing.assert_array_equal(L[3:6], L1[3:6])
+    # and the weighted gradient still matches finite differences
+    orc.set_component_weights(w)
+    try:
+        pbt = wl.tiny(dim=3, width=4, depth=2, seed=5)
+        a = problem_arrays(pbt)
+        t0 = pbt.subs[0].theta.astype(np.float64)
+        _, g = orc.loss_grad(3, 4, 2, pbt.nu, pbt.lam, t0, **a)
+        i = np.argmax(np.abs(g))
+        tp, tm = t0.copy(), t0.copy()
+        tp[i] += 1e-6
+        tm[i] -= 1e-6
+        fd = (orc.loss_grad(3, 4, 2, pbt.nu, pbt.lam, tp, want_grad=False, **a)[0][6]
+              - orc.loss_grad(3, 4, 2, pbt.nu, pbt.lam, tm, want_grad=False, **a)[0][6]) / 2e-6
+        assert fd == pytest.approx(g[i], rel=1e-6)
+    finally:
+        orc.set_component_weights(None)
+
+
+def test_gradient_clipping_closed_form(orc):
+    g = np.array([3.0, 4.0, 0.0, -12.0])          # norm 13
+    c, n = orc.clip_grad(g, 1.0)
+    assert n == 13.0
+    np.testing.assert_allclose(c, g / 13.0, rtol=1e-15)
+    assert np.linalg.norm(c) == pytest.approx(1.0, rel=1e-15)
+    c2, _ = orc.clip_grad(g, 20.0)                 # below the limit: unchanged
+    np.testing.assert_array_equal(c2, g)
+    c3, _ = orc.clip_grad(g, 0.0)                  # 0 disables clipping
+    np.testing.assert_array_equal(c3, g)
+
+
+def test_step_lr_schedule_by_hand(orc):
+    # appendix B 3D cylinder: factor 0.3 every 5k epochs
+    assert orc.step_lr(1e-3, 0.3, 5000, 1) == 1e-3
+    assert orc.step_lr(1e-3, 0.3, 5000, 5000) == 1e-3
+    assert orc.step_lr(1e-3, 0.3, 5000, 5001) == pytest.approx(3e-4, rel=1e-15)
+    assert orc.step_lr(1e-3, 0.3, 5000, 10001) == pytest.approx(9e-5, rel=1e-15)
+    assert orc.step_lr(1e-3, 0.3, 0, 10001) == 1e-3

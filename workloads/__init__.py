@@ -159,6 +159,11 @@ class Problem:
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-8
+    activation: str = "tanh"             # "tanh" or "sin"
+    comp_w: Optional[np.ndarray] = None  # velocity-component weights in L_obs, L_gh_u
+    clip_norm: float = 0.0               # global-norm gradient clipping (0: off)
+    lr_factor: float = 1.0               # step decay of the learning rate
+    lr_interval: int = 0
 
     @property
     def n_params(self) -> int:
@@ -367,3 +372,23 @@ def query_requests(seed: int, n_req: int, rate_hz: float = 200.0, nmax: int = 20
 
 def query_points(rng: np.random.Generator, n: int, lo=(0, 0, 0), hi=(8, 2, 4)) -> np.ndarray:
     return uniform(rng, n, lo, hi)
+
+
+def cylinder3d_recipe(seed: int = 0, n_pde: int = 250_000, n_obs: int = 20_000,
+                      n_gh_face: int = 4000, width: int = 128, depth: int = 8) -> Problem:
+    """The 3D workload trained with the paper's 3D-cylinder recipe (section 3.3,
+    appendix B): sin activation, velocity-component weights (1, 5, 100) in
+    L_obs and L_gh_u, global-norm clipping at 1.0, learning rate 1e-3 decayed
+    by 0.3 every 5,000 steps.  Data as config4 (Ethier-Steinman)."""
+    pb = config4(seed, n_pde=n_pde, n_obs=n_obs, n_gh_face=n_gh_face)
+    if width != 128 or depth != 8:
+        for s in pb.subs:
+            s.theta = xavier_theta(3, width, depth, seed)
+        pb.width, pb.depth = width, depth
+    pb.name = f"cylinder3d_recipe_3d_{depth}x{width}"
+    pb.activation = "sin"
+    pb.comp_w = np.array([1.0, 5.0, 100.0])
+    pb.clip_norm = 1.0
+    pb.lr_factor = 0.3
+    pb.lr_interval = 5000
+    return pb
