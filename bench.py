@@ -42,6 +42,7 @@ WORKLOADS = {
     "config2": "config2_2d_8x100_100k",
     "config3": "config3_16x2d_6x64",
     "config4": "config4_3d_8x128_250k",
+    "cylinder3d": "cylinder3d_recipe_3d_8x128_250k_sin",
 }
 
 
@@ -76,7 +77,7 @@ def algorithmic_bytes(pb):
 def make_problem(name, seed=0):
     import workloads as wl
     return {"config1": wl.config1, "config2": wl.config2, "config3": wl.config3,
-            "config4": wl.config4}[name](seed)
+            "config4": wl.config4, "cylinder3d": wl.cylinder3d_recipe}[name](seed)
 
 
 def kernel_source_hash():
@@ -232,6 +233,23 @@ def main():
     traffic = traffic_from_profiles(args.workload)
 
     extra = {}
+    faces = [(a, b, first, count) for a, sd in enumerate(pb.subs) for (b, _k, first, count) in sd.faces]
+    if faces:
+        # on-device ghost-target exchange (value forward of every neighbour on
+        # its faces, anchor subtraction for master senders), HIP events
+        targets = [sd.gh_up if sd.gh_up.numel() else None for sd in ctx.subs]
+        ctx.exchange(faces, pb.x_anc, targets)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            ctx.exchange(faces, pb.x_anc, targets)
+        e1.record()
+        torch.cuda.synchronize()
+        n_gh = sum(c for (_a, _b, _f, c) in faces)
+        ms = e0.elapsed_time(e1) / args.steps
+        extra["exchange"] = {"ms": ms, "ghost_points": n_gh, "faces": len(faces),
+                             "points_per_s": n_gh / (ms * 1e-3)}
     if args.per_subdomain and len(pb.subs) > 1:
         ctx.kernel_time()
         for k in range(args.steps):
@@ -259,6 +277,7 @@ def main():
                    "n_value_points": int(sum(s.obs_x.shape[0] + s.gh_x.shape[0] + s.anc_x.shape[0]
                                              for s in pb.subs)),
                    "gflop_per_step": flops / 1e9, "tile_points": info["tile_points"],
+                   "activation": pb.activation,
                    "workgroups": info["n_wg"], "graph": True, "losses_finite": finite},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA_TFLOPS,

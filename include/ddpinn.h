@@ -187,6 +187,25 @@ pinn_status pinn_exchange(pinn_ctx *ctx, const pinn_face *faces, int32_t n_faces
  */
 pinn_status pinn_kernel_time(pinn_ctx *ctx, double *total_ms, int64_t *launches);
 
+/*
+ * Evaluation post-processing (section 3: stitching of local experts, the
+ * master-rank anchor pinning p - p(x_anc, t), removal of the spatial mean of
+ * pressure at each time, relative L2 error).  Points x[n][d+1] and the
+ * reference ref[n][d+1] = (u_1..u_d, p) are grouped in snapshots: snapshot k
+ * holds points snap_off[k] .. snap_off[k+1]-1 (host array, n_snap + 1
+ * entries, nondecreasing, snap_off[n_snap] == n).  Writes err_out (device,
+ * d + 2 floats): relative L2 of u_1..u_d, of the velocity vector, and of the
+ * processed pressure.  Every point must lie in some subdomain box (else the
+ * errors are NaN).  x_anc: host [d].  scratch of
+ * pinn_evaluate_scratch_bytes(ctx, n, n_snap, max_snapshot_points) bytes.
+ * Synchronizes `stream` once after copying snap_off.
+ */
+size_t pinn_evaluate_scratch_bytes(const pinn_ctx *ctx, int64_t n, int32_t n_snap,
+                                   int64_t max_snapshot_points);
+pinn_status pinn_evaluate(pinn_ctx *ctx, const float *x, const float *ref, int64_t n,
+                          const int64_t *snap_off, int32_t n_snap, const float *x_anc,
+                          float *err_out, void *scratch, size_t scratch_bytes, void *stream);
+
 /* Rebuild the kernels' weight copies after theta was written outside pinn_step. */
 pinn_status pinn_refresh(pinn_ctx *ctx, void *stream);
 

@@ -17,6 +17,8 @@ Functions and the passages they follow:
 * :func:`route`, :func:`query2d` -- stitching of local experts (section 3).
 * :func:`exchange`  -- ghost targets with reference anchor normalisation
   (section 2.2, anchor-normalised pressure; Algorithm 1 exchange branch).
+* :func:`evaluate`  -- relative L2 errors after stitching, master anchor
+  pinning and per-snapshot pressure-mean removal (section 3).
 """
 from __future__ import annotations
 
@@ -69,6 +71,7 @@ def lib():
         L.or_route.argtypes = [_i, _i, _p, _p, _l, _p]
         L.or_query2d.argtypes = [_i, _i, _i, _p, _p, _p, _l, _p]
         L.or_exchange.argtypes = [_i, _i, _i, _p, _i, _p, _p, _l, _p]
+        L.or_evaluate.argtypes = [_i, _i, _i, _i, _p, _p, _p, _p, _p, _l, _p, _p, _i, _p]
         L.or_set_activation.argtypes = [_i]
         L.or_set_component_weights.argtypes = [_p]
         L.or_clip_grad.restype = _d
@@ -232,3 +235,20 @@ def clip_grad(g, c):
 
 def step_lr(lr, factor, interval, t):
     return float(lib().or_step_lr(float(lr), float(factor), int(interval), int(t)))
+
+
+def evaluate(dim, width, depth, thetas, is_master, boxes, x_anc, x, ref, snap_off):
+    """Relative L2 errors after stitching, master anchor pinning and
+    per-snapshot pressure mean removal: [u_1..u_d, velocity, p]."""
+    ths = [_f64(t) for t in thetas]
+    arr = (_p * len(ths))(*[t.ctypes.data_as(_p) for t in ths])
+    mst = np.ascontiguousarray(np.asarray(is_master, dtype=np.int32))
+    b = _f64(boxes)
+    xa = _f64(x_anc).reshape(-1)
+    x = _f64(x).reshape(-1, dim + 1)
+    r = _f64(ref).reshape(-1, dim + 1)
+    so = np.ascontiguousarray(np.asarray(snap_off, dtype=np.int64))
+    err = np.zeros(dim + 2)
+    lib().or_evaluate(dim, width, depth, len(ths), arr, mst.ctypes.data_as(_p), _ptr(b), _ptr(xa),
+                      _ptr(x), x.shape[0], _ptr(r), so.ctypes.data_as(_p), so.size - 1, _ptr(err))
+    return err

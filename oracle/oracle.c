@@ -28,7 +28,10 @@
  *   - point queries: routing to the half-open subdomain box and (u, v, p, w)
  *     with vorticity w = v_x - u_y (section 3, stitching of local experts),
  *   - the ghost-target exchange with reference anchor normalisation
- *     (section 2.2, anchor-normalised pressure; Algorithm 1, exchange branch).
+ *     (section 2.2, anchor-normalised pressure; Algorithm 1, exchange branch),
+ *   - evaluation post-processing: stitched predictions, master anchor
+ *     pinning, per-snapshot spatial-mean removal, relative L2 errors
+ *     (section 3, relative L2 equation and pressure post-processing).
  *
  * Conventions (readings where the paper is silent):
  *   inputs xi = (x_1..x_d, t); outputs y = (u_1..u_d, p)
@@ -596,4 +599,73 @@ void or_exchange(int dim, int W, int H, const double *theta_nb, int nb_is_master
     }
     free(z); free(h);
   }
+}
+
+/*
+ * Evaluation post-processing (section 3, relative L2 error equation and the
+ * pressure post-processing that follows it).  Points x[n][d_in] are grouped
+ * in snapshots: snapshot k holds points snap_off[k] .. snap_off[k+1]-1.
+ *   1. predictions of the subdomain each point routes to (stitching),
+ *   2. points in master subdomains: p~ = p - p(x_anc, t) with the same network,
+ *   3. per snapshot, the spatial mean of p~ and of the reference p is removed,
+ *   4. err[i] = ||u_i,pred - u_i,ref|| / ||u_i,ref|| (i < d),
+ *      err[d] = the same over all velocity components together,
+ *      err[d+1] = the same for the processed pressure.
+ * ref[n][d_in] = (u_1..u_d, p).  thetas[s], is_master[s] per subdomain.
+ */
+void or_evaluate(int dim, int W, int H, int n_sub, const double *const *thetas,
+                 const int *is_master, const double *boxes, const double *x_anc,
+                 const double *x, long n, const double *ref, const long *snap_off, int n_snap,
+                 double *err) {
+  const int D = dim + 1;
+  int *sub = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  double *pred = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1) * D);
+  or_route(dim, n_sub, boxes, x, n, sub);
+#pragma omp parallel
+  {
+    double *z = malloc(sizeof(double) * (size_t)H * W);
+    double *h = malloc(sizeof(double) * (size_t)H * W);
+    double y[4], ya[4], xa[4];
+#pragma omp for schedule(static)
+    for (long p = 0; p < n; p++) {
+      if (sub[p] < 0) { for (int o = 0; o < D; o++) pred[p * D + o] = NAN; continue; }
+      net_t nt; net_init(&nt, dim, W, H, thetas[sub[p]]);
+      forward_point(&nt, x + p * D, 1, z, h, y);
+      for (int o = 0; o < D; o++) pred[p * D + o] = y[o];
+      if (is_master[sub[p]]) {
+        for (int a = 0; a < dim; a++) xa[a] = x_anc[a];
+        xa[dim] = x[p * D + dim];
+        forward_point(&nt, xa, 1, z, h, ya);
+        pred[p * D + dim] -= ya[dim];
+      }
+    }
+    free(z); free(h);
+  }
+  double num[4] = {0, 0, 0, 0}, den[4] = {0, 0, 0, 0}, nump = 0.0, denp = 0.0;
+  for (int k = 0; k < n_snap; k++) {
+    long a = snap_off[k], b = snap_off[k + 1];
+    double mp = 0.0, mr = 0.0;
+    for (long p = a; p < b; p++) { mp += pred[p * D + dim]; mr += ref[p * D + dim]; }
+    if (b > a) { mp /= (double)(b - a); mr /= (double)(b - a); }
+    for (long p = a; p < b; p++) {
+      for (int i = 0; i < dim; i++) {
+        double e = pred[p * D + i] - ref[p * D + i];
+        num[i] += e * e;
+        den[i] += ref[p * D + i] * ref[p * D + i];
+      }
+      double ep = (pred[p * D + dim] - mp) - (ref[p * D + dim] - mr);
+      double rp = ref[p * D + dim] - mr;
+      nump += ep * ep;
+      denp += rp * rp;
+    }
+  }
+  double nv = 0.0, dv = 0.0;
+  for (int i = 0; i < dim; i++) {
+    err[i] = sqrt(num[i] / den[i]);
+    nv += num[i];
+    dv += den[i];
+  }
+  err[dim] = sqrt(nv / dv);
+  err[dim + 1] = sqrt(nump / denp);
+  free(sub); free(pred);
 }

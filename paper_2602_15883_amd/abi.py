@@ -32,7 +32,8 @@ PINN_Q_RESIDUAL = 3
 # every symbol include/ddpinn.h declares
 EXPORTS = ("pinn_num_params", "pinn_create", "pinn_step", "pinn_query_scratch_bytes",
            "pinn_query", "pinn_exchange", "pinn_refresh", "pinn_destroy",
-           "pinn_get_launch_info", "pinn_last_error", "pinn_kernel_time")
+           "pinn_get_launch_info", "pinn_last_error", "pinn_kernel_time",
+           "pinn_evaluate_scratch_bytes", "pinn_evaluate")
 
 
 class PinnError(RuntimeError):
@@ -98,6 +99,11 @@ def lib():
                                 POINTER(c_void_p), c_void_p]
     L.pinn_kernel_time.restype = c_int32
     L.pinn_kernel_time.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
+    L.pinn_evaluate_scratch_bytes.restype = c_size_t
+    L.pinn_evaluate_scratch_bytes.argtypes = [c_void_p, c_int64, c_int32, c_int64]
+    L.pinn_evaluate.restype = c_int32
+    L.pinn_evaluate.argtypes = [c_void_p, c_void_p, c_void_p, c_int64, POINTER(c_int64), c_int32,
+                                POINTER(c_float), c_void_p, c_void_p, c_size_t, c_void_p]
     L.pinn_refresh.restype = c_int32
     L.pinn_refresh.argtypes = [c_void_p, c_void_p]
     L.pinn_destroy.restype = c_int32

@@ -212,6 +212,24 @@ class Context:
         check(lib().pinn_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
 
+    def evaluate(self, x: torch.Tensor, ref: torch.Tensor, snap_off, x_anc, stream=None):
+        """Relative L2 errors [u_1..u_d, velocity, p] after stitching, master
+        anchor pinning and per-snapshot pressure-mean removal (section 3)."""
+        n = x.shape[0]
+        off = np.ascontiguousarray(np.asarray(snap_off, dtype=np.int64))
+        n_snap = off.size - 1
+        max_snap = int(np.max(np.diff(off))) if n_snap else 0
+        need = int(lib().pinn_evaluate_scratch_bytes(self._h, n, n_snap, max_snap))
+        scratch = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        base = scratch.data_ptr()
+        adj = (-base) % 256
+        err = torch.empty(self.dim + 2, dtype=torch.float32, device=self.device)
+        xa = (ctypes.c_float * 3)(*[float(v) for v in list(x_anc)[:3]])
+        check(lib().pinn_evaluate(self._h, _ptr(x), _ptr(ref), n,
+                                  off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n_snap, xa,
+                                  _ptr(err), base + adj, scratch.numel() - adj, _stream(stream)))
+        return err
+
     def refresh(self, stream=None):
         check(lib().pinn_refresh(self._h, _stream(stream)))
 

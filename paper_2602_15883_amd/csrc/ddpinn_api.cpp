@@ -789,6 +789,102 @@ pinn_status pinn_kernel_time(pinn_ctx* c, double* total_ms, int64_t* launches) {
   return PINN_OK;
 }
 
+size_t pinn_evaluate_scratch_bytes(const pinn_ctx* c, int64_t n, int32_t n_snap, int64_t max_snap) {
+  if (!c || n < 0 || n_snap < 1 || max_snap < 0) return 0;
+  const int D = c->sh.D;
+  const int64_t nblk = std::max<int64_t>(1, (max_snap + kEvalChunk - 1) / kEvalChunk);
+  return pinn_query_scratch_bytes(c, n) + 3 * align256(sizeof(float) * (size_t)n * D) +
+         align256(sizeof(int64_t) * (n_snap + 1)) + align256(sizeof(float) * 2 * n_snap * nblk) +
+         align256(sizeof(float) * 2 * (D + 1) * n_snap * nblk);
+}
+
+pinn_status pinn_evaluate(pinn_ctx* c, const float* x, const float* ref, int64_t n, const int64_t* snap_off,
+                          int32_t n_snap, const float* x_anc, float* err_out, void* scratch,
+                          size_t scratch_bytes, void* stream) {
+  g_err.clear();
+  if (!c) return fail(PINN_E_INVAL, "ctx is NULL");
+  if (n < 1 || !x || !ref || !snap_off || n_snap < 1 || !x_anc || !err_out)
+    return fail(PINN_E_INVAL, "bad evaluation arguments");
+  if (snap_off[0] != 0 || snap_off[n_snap] != n) return fail(PINN_E_INVAL, "snap_off must run from 0 to n");
+  int64_t max_snap = 0;
+  for (int k = 0; k < n_snap; ++k) {
+    if (snap_off[k + 1] < snap_off[k]) return fail(PINN_E_INVAL, "snap_off must be nondecreasing");
+    max_snap = std::max(max_snap, snap_off[k + 1] - snap_off[k]);
+  }
+  if (n > c->cfg.max_query_points) return fail(PINN_E_BUDGET, "evaluation of %lld points exceeds max_query_points", (long long)n);
+  const size_t need = pinn_evaluate_scratch_bytes(c, n, n_snap, max_snap);
+  if (!scratch || scratch_bytes < need) return fail(PINN_E_NOMEM, "evaluation scratch needs %zu bytes", need);
+  if ((uintptr_t)scratch & 255) return fail(PINN_E_INVAL, "scratch must be 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  const Shape& sh = c->sh;
+  const int D = sh.D;
+  char* p = (char*)scratch;
+  char* qscr = p;
+  p += pinn_query_scratch_bytes(c, n);
+  float* pred = (float*)p; p += align256(sizeof(float) * (size_t)n * D);
+  float* xa = (float*)p;   p += align256(sizeof(float) * (size_t)n * D);
+  float* pa = (float*)p;   p += align256(sizeof(float) * (size_t)n * D);
+  int64_t* d_off = (int64_t*)p; p += align256(sizeof(int64_t) * (n_snap + 1));
+  const int nblk = (int)std::max<int64_t>(1, (max_snap + kEvalChunk - 1) / kEvalChunk);
+  float* mpart = (float*)p; p += align256(sizeof(float) * 2 * n_snap * nblk);
+  float* epart = (float*)p;
+  // routing shared by both value queries
+  RouteArgs ra{};
+  ra.x = x;
+  ra.n = n;
+  ra.boxes = c->d_boxes;
+  for (int q = 0; q < 4; ++q) ra.gmax[q] = c->gmax[q];
+  ra.n_sub = c->n_sub;
+  ra.D = D;
+  ra.out_cols = D;
+  char* r = qscr;
+  ra.sub_id = (int32_t*)r;  r += align256(4 * (size_t)n);
+  ra.perm = (int32_t*)r;    r += align256(4 * (size_t)n);
+  ra.counts = (int32_t*)r;  r += align256(4 * (size_t)(c->n_sub + 1));
+  ra.cursor = (int32_t*)r;  r += align256(4 * (size_t)(c->n_sub + 1));
+  ra.offsets = (int32_t*)r;
+  ra.out = pred;
+  HIPCHECK(launch_route(ra, s));
+  QueryArgs qa{};
+  qa.sh = sh;
+  qa.subs = c->d_subs;
+  qa.x = x;
+  qa.out = pred;
+  qa.perm = ra.perm;
+  qa.counts = ra.counts;
+  qa.offsets = ra.offsets;
+  qa.n = n;
+  qa.sub = -1;
+  qa.n_sub = c->n_sub;
+  qa.what = Q_VALUE;
+  qa.nu = (float)c->cfg.nu;
+  qa.lds_floats = c->qlds_floats;
+  const int npts = 16 * (2 * sh.dim + 2);
+  const int nwg = (int)std::min<int64_t>((n + npts - 1) / npts + c->n_sub, (int64_t)c->num_cu * c->query_occ);
+  HIPCHECK(launch_query(qa, nwg, s));
+  HIPCHECK(launch_anchor_points(x, n, D, x_anc, xa, s));
+  qa.x = xa;
+  qa.out = pa;
+  HIPCHECK(launch_query(qa, nwg, s));
+  HIPCHECK(hipMemcpyAsync(d_off, snap_off, sizeof(int64_t) * (n_snap + 1), hipMemcpyHostToDevice, s));
+  EvalArgs ea{};
+  ea.subs = c->d_subs;
+  ea.pred = pred;
+  ea.pa = pa;
+  ea.ref = ref;
+  ea.sub_id = ra.sub_id;
+  ea.snap_off = d_off;
+  ea.mpart = mpart;
+  ea.epart = epart;
+  ea.err_out = err_out;
+  ea.D = D;
+  ea.n_snap = n_snap;
+  ea.nblk = nblk;
+  HIPCHECK(launch_evaluate(ea, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  return PINN_OK;
+}
+
 pinn_status pinn_refresh(pinn_ctx* c, void* stream) {
   g_err.clear();
   if (!c) return fail(PINN_E_INVAL, "ctx is NULL");

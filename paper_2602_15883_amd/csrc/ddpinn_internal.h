@@ -166,6 +166,21 @@ struct ExchangeArgs {
   int32_t pad_;
 };
 
+// Evaluation post-processing: per-snapshot pressure means and error sums.
+constexpr int kEvalChunk = 1024;   // points per block in the evaluation kernels
+struct EvalArgs {
+  const SubDev* subs;
+  const float* pred;        // [n][D] routed predictions
+  const float* pa;          // [n][D] predictions at (x_anc, t) by the same subdomain
+  const float* ref;         // [n][D] reference (u.., p)
+  const int32_t* sub_id;    // [n]
+  const int64_t* snap_off;  // [n_snap + 1]
+  float* mpart;             // [n_snap][nblk][2] sums of processed p and reference p
+  float* epart;             // [n_snap][nblk][2 * (D + 1)] error sums
+  float* err_out;           // [D + 1]
+  int32_t D, n_snap, nblk, pad_;
+};
+
 // Launchers (ddpinn_kernels.hip)
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int tile_points, int n_wg, hipStream_t s);
@@ -173,6 +188,8 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_route(const RouteArgs& a, hipStream_t s);
 hipError_t launch_query(const QueryArgs& a, int n_wg, hipStream_t s);
 hipError_t launch_exchange(const ExchangeArgs& a, int n_wg, hipStream_t s);
+hipError_t launch_anchor_points(const float* x, int64_t n, int D, const float* x_anc, float* xa, hipStream_t s);
+hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s);
 
 // Kernel entry points and their LDS needs (for graph nodes and occupancy).
 const void* step_kernel_ptr(int dim, int tile_points, int act);

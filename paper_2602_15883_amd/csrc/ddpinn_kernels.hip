@@ -1169,6 +1169,135 @@ __global__ __launch_bounds__(512) void exchange_kernel(const ExchangeArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// evaluation post-processing (stitched field, master anchor pinning,
+// per-snapshot pressure-mean removal, relative L2 errors)
+// ---------------------------------------------------------------------------
+__global__ void anchor_points_kernel(const float* x, int64_t n, int D, float a0, float a1, float a2, float* xa) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float an[3] = {a0, a1, a2};
+  for (int q = 0; q < D - 1; ++q) xa[i * D + q] = an[q];
+  xa[i * D + D - 1] = x[i * D + D - 1];   // the point's own time
+}
+
+__device__ __forceinline__ float block_sum256(float v, float* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const float r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// processed pressure of point i: p - p(x_anc, t) on master subdomains
+__device__ __forceinline__ float eval_p(const EvalArgs& a, int64_t i) {
+  const int D = a.D;
+  float p = a.pred[i * D + D - 1];
+  const int s = a.sub_id[i];
+  if (s >= 0 && a.subs[s].is_master) p -= a.pa[i * D + D - 1];
+  return p;
+}
+
+__global__ void eval_means_kernel(const EvalArgs a) {
+  __shared__ float red[256];
+  const int k = blockIdx.y;
+  const int64_t b0 = a.snap_off[k], b1 = a.snap_off[k + 1];
+  const int64_t lo = b0 + (int64_t)blockIdx.x * kEvalChunk;
+  const int64_t hi = min(b1, lo + kEvalChunk);
+  float sp = 0.f, sr = 0.f;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    sp += eval_p(a, i);
+    sr += a.ref[i * a.D + a.D - 1];
+  }
+  sp = block_sum256(sp, red);
+  sr = block_sum256(sr, red);
+  if (threadIdx.x == 0) {
+    a.mpart[((size_t)k * a.nblk + blockIdx.x) * 2 + 0] = sp;
+    a.mpart[((size_t)k * a.nblk + blockIdx.x) * 2 + 1] = sr;
+  }
+}
+
+__global__ void eval_err_kernel(const EvalArgs a) {
+  __shared__ float red[256];
+  const int k = blockIdx.y, D = a.D, dim = D - 1;
+  const int64_t b0 = a.snap_off[k], b1 = a.snap_off[k + 1];
+  float mp = 0.f, mr = 0.f;
+  for (int b = 0; b < a.nblk; ++b) {
+    mp += a.mpart[((size_t)k * a.nblk + b) * 2 + 0];
+    mr += a.mpart[((size_t)k * a.nblk + b) * 2 + 1];
+  }
+  if (b1 > b0) {
+    mp /= (float)(b1 - b0);
+    mr /= (float)(b1 - b0);
+  }
+  const int64_t lo = b0 + (int64_t)blockIdx.x * kEvalChunk;
+  const int64_t hi = min(b1, lo + kEvalChunk);
+  float num[4] = {0.f, 0.f, 0.f, 0.f}, den[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+    for (int q = 0; q < dim; ++q) {
+      const float r = a.ref[i * D + q], e = a.pred[i * D + q] - r;
+      num[q] += e * e;
+      den[q] += r * r;
+    }
+    const float r = a.ref[i * D + dim] - mr;
+    const float e = (eval_p(a, i) - mp) - r;
+    num[dim] += e * e;
+    den[dim] += r * r;
+  }
+  float* out = a.epart + ((size_t)k * a.nblk + blockIdx.x) * 2 * (D + 1);
+  for (int q = 0; q < D; ++q) {
+    const float vn = block_sum256(num[q], red);
+    const float vd = block_sum256(den[q], red);
+    if (threadIdx.x == 0) {
+      out[2 * q] = vn;
+      out[2 * q + 1] = vd;
+    }
+  }
+}
+
+// err[q] (velocity components), err[dim] (velocity vector), err[dim+1] (p)
+__global__ void eval_final_kernel(const EvalArgs a) {
+  if (threadIdx.x != 0) return;
+  const int D = a.D, dim = D - 1;
+  float num[4] = {0.f, 0.f, 0.f, 0.f}, den[4] = {0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < a.n_snap; ++k)
+    for (int b = 0; b < a.nblk; ++b) {
+      const float* e = a.epart + ((size_t)k * a.nblk + b) * 2 * (D + 1);
+      for (int q = 0; q < D; ++q) {
+        num[q] += e[2 * q];
+        den[q] += e[2 * q + 1];
+      }
+    }
+  float nv = 0.f, dv = 0.f;
+  for (int q = 0; q < dim; ++q) {
+    a.err_out[q] = sqrtf(num[q] / den[q]);
+    nv += num[q];
+    dv += den[q];
+  }
+  a.err_out[dim] = sqrtf(nv / dv);
+  a.err_out[dim + 1] = sqrtf(num[dim] / den[dim]);
+}
+
+hipError_t launch_anchor_points(const float* x, int64_t n, int D, const float* x_anc, float* xa, hipStream_t s) {
+  const unsigned nb = (unsigned)((n + 255) / 256);
+  if (nb)
+    hipLaunchKernelGGL(anchor_points_kernel, dim3(nb), dim3(256), 0, s, x, n, D, x_anc[0], D > 2 ? x_anc[1] : 0.f,
+                       D > 3 ? x_anc[2] : 0.f, xa);
+  return hipGetLastError();
+}
+
+hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s) {
+  const dim3 grid(a.nblk, a.n_snap);
+  hipLaunchKernelGGL(eval_means_kernel, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(eval_err_kernel, grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL(eval_final_kernel, dim3(1), dim3(64), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 int step_value_points(int dim, int tile_points) {

@@ -527,3 +527,62 @@ def test_step_lr_schedule_by_hand(orc):
     assert orc.step_lr(1e-3, 0.3, 5000, 5001) == pytest.approx(3e-4, rel=1e-15)
     assert orc.step_lr(1e-3, 0.3, 5000, 10001) == pytest.approx(9e-5, rel=1e-15)
     assert orc.step_lr(1e-3, 0.3, 0, 10001) == 1e-3
+
+
+# ------------------------------------------------ evaluation post-processing
+def _eval_setup(orc, masters=(0, 4, 8, 12)):
+    boxes, thetas = wl.serving_nets(seed=4, width=6, depth=2)
+    is_master = [s in masters for s in range(len(thetas))]
+    rng = np.random.default_rng(12)
+    # 3 snapshots on a uniform spatial grid at t = 0.25, 1.5, 2.75
+    gx, gy = np.meshgrid(np.linspace(0.05, 7.95, 20), np.linspace(0.05, 1.95, 8))
+    pts, off = [], [0]
+    for t in (0.25, 1.5, 2.75):
+        pts.append(np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, t)], 1))
+        off.append(off[-1] + gx.size)
+    x = np.concatenate(pts)
+    return boxes, thetas, is_master, x, np.array(off), rng
+
+
+def test_evaluation_identity_gives_zero_error(orc):
+    """Reference = the stitched raw network output: velocity errors vanish, and
+    with every subdomain of a snapshot a master the anchor offset is constant
+    per snapshot, so mean removal cancels it and the pressure error vanishes."""
+    boxes, thetas, _, x, off, _ = _eval_setup(orc)
+    every = [True] * len(thetas)
+    sub = orc.route(2, boxes, x)
+    ref = np.array([orc.values(2, 6, 2, thetas[s], x[i:i + 1])[0] for i, s in enumerate(sub)])
+    # one master subdomain per snapshot region: restrict x to the first strip
+    keep = (x[:, 0] < 2.0)
+    xs, rs = x[keep], ref[keep]
+    offs = np.concatenate([[0], np.cumsum([np.sum(keep[off[k]:off[k + 1]]) for k in range(3)])])
+    err = orc.evaluate(2, 6, 2, thetas, every, boxes, [1.0, 1.0], xs, rs, offs)
+    assert np.all(err[:3] == 0.0)
+    assert err[3] < 1e-13
+
+
+def test_evaluation_closed_forms(orc):
+    boxes, thetas, is_master, x, off, rng = _eval_setup(orc)
+    sub = orc.route(2, boxes, x)
+    raw = np.array([orc.values(2, 6, 2, thetas[s], x[i:i + 1])[0] for i, s in enumerate(sub)])
+    # processed prediction by hand: anchor subtraction on masters
+    pred = raw.copy()
+    for i, s in enumerate(sub):
+        if is_master[s]:
+            pred[i, 2] -= orc.values(2, 6, 2, thetas[s], np.array([[1.0, 1.0, x[i, 2]]]))[0, 2]
+    # reference = 2 x processed prediction: every relative error is 1/2
+    ref = 2.0 * pred
+    err = orc.evaluate(2, 6, 2, thetas, is_master, boxes, [1.0, 1.0], x, ref, off)
+    np.testing.assert_allclose(err, 0.5, rtol=1e-12)
+    # a per-snapshot constant added to the reference pressure changes nothing
+    ref2 = ref.copy()
+    for k, c in enumerate([3.0, -7.0, 0.5]):
+        ref2[off[k]:off[k + 1], 2] += c
+    err2 = orc.evaluate(2, 6, 2, thetas, is_master, boxes, [1.0, 1.0], x, ref2, off)
+    np.testing.assert_allclose(err2, err, rtol=1e-12)
+    # but a non-constant pressure change does
+    ref3 = ref.copy()
+    ref3[:, 2] += x[:, 0]
+    err3 = orc.evaluate(2, 6, 2, thetas, is_master, boxes, [1.0, 1.0], x, ref3, off)
+    assert abs(err3[3] - err[3]) > 1e-3
+    np.testing.assert_array_equal(err3[:3], err[:3])
