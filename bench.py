@@ -166,6 +166,40 @@ def query_bench(seconds, seed=0, rate=200.0, budget=32 << 30):
     return st
 
 
+def eval_bench(seed=0, n_snap=40, per_snap=50_000, reps=5):
+    """Evaluation post-processing (section 3) over the resident serving
+    networks: n_snap snapshots of per_snap points, Taylor-Green reference."""
+    import torch
+
+    import workloads as wl
+    from paper_2602_15883_amd.serve import serving_context
+    boxes, thetas = wl.serving_nets(seed, width=100, depth=8)
+    masters = [s % 4 == 0 for s in range(len(thetas))]
+    n = n_snap * per_snap
+    ctx = serving_context(boxes, thetas, 100, 8, device="cuda", masters=masters,
+                          max_query_points=max(n, 1 << 22))
+    rng = np.random.default_rng([seed, 11])
+    x = wl.uniform(rng, n, (0, 0, 0), (8, 2, 4))
+    x[:, 2] = np.repeat((np.arange(n_snap) + 0.5) * 4.0 / n_snap, per_snap)
+    u, v, p = wl.taylor_green(x[:, 0].astype(np.float64), x[:, 1], x[:, 2])
+    ref = np.stack([u, v, p], axis=1).astype(np.float32)
+    off = np.arange(n_snap + 1, dtype=np.int64) * per_snap
+    xd, rd = torch.from_numpy(x).cuda(), torch.from_numpy(ref).cuda()
+    err = ctx.evaluate(xd, rd, off, [1.0, 1.0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        err = ctx.evaluate(xd, rd, off, [1.0, 1.0])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    e = err.cpu().numpy()
+    ctx.close()
+    return {"ms": dt * 1e3, "points": n, "snapshots": n_snap, "points_per_s": n / dt,
+            "rel_l2": {"u": float(e[0]), "v": float(e[1]), "velocity": float(e[2]), "p": float(e[3])},
+            "workload": "16 x 2d 3->8x100->3 (untrained), masters = first strip, "
+                        f"{n_snap} snapshots x {per_snap} points, Taylor-Green reference"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,6 +211,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--query-seconds", type=float, default=8.0)
     ap.add_argument("--no-query", action="store_true")
+    ap.add_argument("--no-eval", action="store_true")
     ap.add_argument("--per-subdomain", action="store_true",
                     help="also time one plain launch per subdomain (grouped vs plain)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -290,6 +325,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(pb)
     if not args.no_query:
         out["query"] = query_bench(args.query_seconds, seed=args.seed)
+    if not args.no_eval:
+        out["evaluate"] = eval_bench(seed=args.seed)
     print(json.dumps(out), flush=True)
 
 

@@ -794,7 +794,8 @@ size_t pinn_evaluate_scratch_bytes(const pinn_ctx* c, int64_t n, int32_t n_snap,
   const int D = c->sh.D;
   const int64_t nblk = std::max<int64_t>(1, (max_snap + kEvalChunk - 1) / kEvalChunk);
   return pinn_query_scratch_bytes(c, n) + 3 * align256(sizeof(float) * (size_t)n * D) +
-         align256(sizeof(int64_t) * (n_snap + 1)) + align256(sizeof(float) * 2 * n_snap * nblk) +
+         align256(sizeof(int64_t) * (n_snap + 1)) + align256(sizeof(int32_t) * (c->n_sub + 1)) +
+         align256(sizeof(float) * 2 * n_snap * nblk) +
          align256(sizeof(float) * 2 * (D + 1) * n_snap * nblk);
 }
 
@@ -825,6 +826,7 @@ pinn_status pinn_evaluate(pinn_ctx* c, const float* x, const float* ref, int64_t
   float* xa = (float*)p;   p += align256(sizeof(float) * (size_t)n * D);
   float* pa = (float*)p;   p += align256(sizeof(float) * (size_t)n * D);
   int64_t* d_off = (int64_t*)p; p += align256(sizeof(int64_t) * (n_snap + 1));
+  int32_t* mcounts = (int32_t*)p; p += align256(sizeof(int32_t) * (c->n_sub + 1));
   const int nblk = (int)std::max<int64_t>(1, (max_snap + kEvalChunk - 1) / kEvalChunk);
   float* mpart = (float*)p; p += align256(sizeof(float) * 2 * n_snap * nblk);
   float* epart = (float*)p;
@@ -862,9 +864,12 @@ pinn_status pinn_evaluate(pinn_ctx* c, const float* x, const float* ref, int64_t
   const int npts = 16 * (2 * sh.dim + 2);
   const int nwg = (int)std::min<int64_t>((n + npts - 1) / npts + c->n_sub, (int64_t)c->num_cu * c->query_occ);
   HIPCHECK(launch_query(qa, nwg, s));
+  // p(x_anc, t) by the same network, only where that network is a master
   HIPCHECK(launch_anchor_points(x, n, D, x_anc, xa, s));
+  HIPCHECK(launch_master_counts(c->d_subs, ra.counts, c->n_sub, mcounts, s));
   qa.x = xa;
   qa.out = pa;
+  qa.counts = mcounts;
   HIPCHECK(launch_query(qa, nwg, s));
   HIPCHECK(hipMemcpyAsync(d_off, snap_off, sizeof(int64_t) * (n_snap + 1), hipMemcpyHostToDevice, s));
   EvalArgs ea{};

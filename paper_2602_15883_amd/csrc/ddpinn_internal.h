@@ -189,6 +189,7 @@ hipError_t launch_route(const RouteArgs& a, hipStream_t s);
 hipError_t launch_query(const QueryArgs& a, int n_wg, hipStream_t s);
 hipError_t launch_exchange(const ExchangeArgs& a, int n_wg, hipStream_t s);
 hipError_t launch_anchor_points(const float* x, int64_t n, int D, const float* x_anc, float* xa, hipStream_t s);
+hipError_t launch_master_counts(const SubDev* subs, const int32_t* counts, int n_sub, int32_t* out, hipStream_t s);
 hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s);
 
 // Kernel entry points and their LDS needs (for graph nodes and occupancy).

@@ -1180,6 +1180,11 @@ __global__ void anchor_points_kernel(const float* x, int64_t n, int D, float a0,
   xa[i * D + D - 1] = x[i * D + D - 1];   // the point's own time
 }
 
+// routed counts kept only for master subdomains (the anchor pass skips the rest)
+__global__ void master_counts_kernel(const SubDev* subs, const int32_t* counts, int n_sub, int32_t* out) {
+  for (int s = threadIdx.x; s < n_sub; s += blockDim.x) out[s] = subs[s].is_master ? counts[s] : 0;
+}
+
 __device__ __forceinline__ float block_sum256(float v, float* red) {
   red[threadIdx.x] = v;
   __syncthreads();
@@ -1286,6 +1291,11 @@ hipError_t launch_anchor_points(const float* x, int64_t n, int D, const float* x
   if (nb)
     hipLaunchKernelGGL(anchor_points_kernel, dim3(nb), dim3(256), 0, s, x, n, D, x_anc[0], D > 2 ? x_anc[1] : 0.f,
                        D > 3 ? x_anc[2] : 0.f, xa);
+  return hipGetLastError();
+}
+
+hipError_t launch_master_counts(const SubDev* subs, const int32_t* counts, int n_sub, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(master_counts_kernel, dim3(1), dim3(256), 0, s, subs, counts, n_sub, out);
   return hipGetLastError();
 }
 

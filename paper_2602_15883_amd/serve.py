@@ -26,22 +26,25 @@ BYTES_PER_POINT = 3 * 4 + 4 * 4 + 2 * 4   # points in, (u, v, p, w) out, routing
 
 
 def serving_context(boxes, thetas, width: int, depth: int, dim: int = 2, nu: float = 0.01,
-                    device="cuda", max_query_points: int = 1 << 22) -> Context:
-    """A context holding only resident networks (no training data)."""
+                    device="cuda", max_query_points: int = 1 << 22, masters=None,
+                    activation: str = "tanh") -> Context:
+    """A context holding only resident networks (no training data); masters[s]
+    marks the subdomains that hold the pressure anchor."""
     subs = []
     dev = torch.device(device)
     D = dim + 1
     for s, th in enumerate(thetas):
         t = torch.from_numpy(np.ascontiguousarray(th, np.float32)).to(dev)
         eD = torch.zeros(0, D, device=dev)
-        subs.append(SubTensors(lo=list(boxes[s][0]), hi=list(boxes[s][1]), is_master=False,
+        subs.append(SubTensors(lo=list(boxes[s][0]), hi=list(boxes[s][1]),
+                               is_master=bool(masters[s]) if masters is not None else False,
                                theta=t, adam_m=torch.zeros_like(t), adam_v=torch.zeros_like(t),
                                pde_x=eD, obs_x=eD, obs_u=torch.zeros(0, dim, device=dev),
                                gh_x=eD, gh_up=eD,
                                gh_kind=torch.zeros(0, dtype=torch.uint8, device=dev),
                                anc_x=eD, anc_p=torch.zeros(0, device=dev)))
     return Context(dim, width, depth, subs, nu, np.zeros(6), graph=False, device=dev,
-                   max_query_points=max_query_points)
+                   max_query_points=max_query_points, activation=activation)
 
 
 @dataclass
