@@ -51,6 +51,9 @@ __device__ __forceinline__ v4f zero4() { return v4f{0.f, 0.f, 0.f, 0.f}; }
 // (flat) accesses would also count against the LDS wait counter, so every
 // LDS wait would also wait for outstanding memory loads.
 #define GLOBAL_AS __attribute__((address_space(1)))
+// read-only for the whole launch (work items, subdomain descriptors): loads
+// through the constant address space become scalar loads
+#define CONST_AS __attribute__((address_space(4)))
 __device__ __forceinline__ v4f ldg4(const float* p) { return *(const GLOBAL_AS v4f*)p; }
 __device__ __forceinline__ float ldg(const float* p) { return *(const GLOBAL_AS float*)p; }
 __device__ __forceinline__ void stg4(float* p, v4f v) { *(GLOBAL_AS v4f*)p = v; }
@@ -270,19 +273,22 @@ __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const
 
 // dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col], t < NNB
 //   Zbar from bufG ([col][neuron], stride S); Hprev from bufHb ([neuron][col], stride S2)
-//   K index of step s in lane group g: g*4*NCB + s
+//   Column of step (s4, q) in lane group g: 16*s4 + 4*g + q.  The four groups
+//   then read Zbar rows 4*S apart (S = Wp + 4 = 4 mod 16, so 16 banks apart):
+//   the 64 lanes of one A read hit 64 distinct banks; a group's B read is 4
+//   contiguous columns of a neuron row (one ds_read_b128).
 template <int NCB, int NNB>
 __device__ __forceinline__ void gemm_dw(const float* bufG, int S, const float* bufHb, int S2,
                                         int w, int g, int j, int nb0, v4f (&dw)[4]) {
-  const float* ab = bufG + (g * 4 * NCB) * S + 16 * w + j;
-  const float* bb = bufHb + (16 * nb0 + j) * S2 + g * 4 * NCB;
+  const float* ab = bufG + (4 * g) * S + 16 * w + j;
+  const float* bb = bufHb + (16 * nb0 + j) * S2 + 4 * g;
   for (int s4 = 0; s4 < NCB; ++s4) {
     float a[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = ab[(4 * s4 + q) * S];
+    for (int q = 0; q < 4; ++q) a[q] = ab[(16 * s4 + q) * S];
     v4f b[NNB];
 #pragma unroll
-    for (int t = 0; t < NNB; ++t) b[t] = *reinterpret_cast<const v4f*>(bb + t * 16 * S2 + 4 * s4);
+    for (int t = 0; t < NNB; ++t) b[t] = *reinterpret_cast<const v4f*>(bb + t * 16 * S2 + 16 * s4);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
@@ -443,7 +449,10 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   const int Wp = sh.Wp, NW = sh.NW, H = sh.H;
   const int K4 = Wp / 16;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int lane = tid & 63, w = tid >> 6, g = lane >> 4, j = lane & 15;
+  // the wave index is uniform across a wave: keeping it in a scalar register
+  // lets every per-wave address (weights, stash, slab) be a scalar base plus
+  // the lane offset instead of a 64-bit vector address per use
+  const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, j = lane & 15;
   const StepLds L = step_lds(D, Wp, H, NCB);
   float* bufH = lds + L.bufH;
   float* bufG = lds + L.bufG;
@@ -462,11 +471,19 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   float lacc[6];
   float dwo = 0.f, dbo = 0.f;
 
-  const int it0 = args.wg_begin[blockIdx.x], it1 = args.wg_begin[blockIdx.x + 1];
+  const int it0 = ((const CONST_AS int32_t*)args.wg_begin)[blockIdx.x];
+  const int it1 = ((const CONST_AS int32_t*)args.wg_begin)[blockIdx.x + 1];
   for (int it = it0; it < it1; ++it) {
     __syncthreads();   // the previous tile's readers of xin/acc1 are done
-    const Item item = args.items[it];
-    const SubDev& sd = args.subs[item.sub];
+    const CONST_AS Item& ir = ((const CONST_AS Item*)args.items)[it];
+    Item item;
+    item.sub = ir.sub;
+    item.kind = ir.kind;
+    item.start = ir.start;
+    item.count = ir.count;
+    item.slab = ir.slab;
+    item.flags = ir.flags;
+    const CONST_AS SubDev& sd = ((const CONST_AS SubDev*)args.subs)[item.sub];
     const float* fr = sd.frag;
     const float* W1p = fr + sh.f_w1;
     const float* bp = fr + sh.f_b;
