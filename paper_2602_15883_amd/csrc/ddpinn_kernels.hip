@@ -58,6 +58,14 @@ __device__ __forceinline__ v4f ldg4(const float* p) { return *(const GLOBAL_AS v
 __device__ __forceinline__ float ldg(const float* p) { return *(const GLOBAL_AS float*)p; }
 __device__ __forceinline__ void stg4(float* p, v4f v) { *(GLOBAL_AS v4f*)p = v; }
 __device__ __forceinline__ void stg(float* p, float v) { *(GLOBAL_AS float*)p = v; }
+// wave-uniform base + 32-bit per-lane byte offset: selects the scalar-base
+// addressing form (one lane-offset register instead of a 64-bit address per lane)
+__device__ __forceinline__ v4f ldg4u(const float* base, uint32_t off) {
+  return *(const GLOBAL_AS v4f*)((const GLOBAL_AS char*)base + off);
+}
+__device__ __forceinline__ void stg4u(float* base, uint32_t off, v4f v) {
+  *(GLOBAL_AS v4f*)((GLOBAL_AS char*)base + off) = v;
+}
 
 // sin and cos with full range reduction (device library)
 __device__ __forceinline__ void sincos_f32(float z, float& s, float& c) { sincosf(z, &s, &c); }
@@ -252,23 +260,30 @@ __device__ __forceinline__ void mfma_step(const v4f a, const float* bb, int S, i
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[q], b[cb][q], acc[cb]);
 }
 
+// a0 = this wave's first weight fragment, ldg4u(afrag, 16 * lane), issued by
+// the caller ahead of time so that its latency is not exposed at the start
+template <int NCB>
+__device__ __forceinline__ void gemm_rows_a0(const float* __restrict__ afrag, v4f a0, const float* bufB,
+                                             int S, int K4, int g, int j, int lane, v4f (&acc)[NCB]) {
+  const float* bb = bufB + j * S + g * (4 * K4);
+  const uint32_t lo = (uint32_t)lane * 16u;
+  // two weight-fragment registers: the fragment of the next step is in
+  // flight while the MFMAs of the current step run
+  int s4 = 0;
+  for (; s4 + 2 <= K4; s4 += 2) {
+    const v4f a1 = ldg4u(afrag + (s4 + 1) * 256, lo);
+    mfma_step<NCB>(a0, bb, S, s4, acc);
+    a0 = ldg4u(afrag + (s4 + 2 < K4 ? s4 + 2 : s4 + 1) * 256, lo);
+    mfma_step<NCB>(a1, bb, S, s4 + 1, acc);
+  }
+  if (s4 < K4) mfma_step<NCB>(a0, bb, S, s4, acc);
+}
+
 template <int NCB>
 __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const float* bufB,
                                           int S, int K4, int g, int j, int lane,
                                           v4f (&acc)[NCB]) {
-  const float* bb = bufB + j * S + g * (4 * K4);
-  const float* ap = afrag + lane * 4;
-  // two weight-fragment registers: the fragment of the next step is in
-  // flight while the MFMAs of the current step run
-  v4f a0 = ldg4(ap);
-  int s4 = 0;
-  for (; s4 + 2 <= K4; s4 += 2) {
-    const v4f a1 = ldg4(ap + (s4 + 1) * 256);
-    mfma_step<NCB>(a0, bb, S, s4, acc);
-    a0 = ldg4(ap + (s4 + 2 < K4 ? s4 + 2 : s4 + 1) * 256);
-    mfma_step<NCB>(a1, bb, S, s4 + 1, acc);
-  }
-  if (s4 < K4) mfma_step<NCB>(a0, bb, S, s4, acc);
+  gemm_rows_a0<NCB>(afrag, ldg4u(afrag, (uint32_t)lane * 16u), bufB, S, K4, g, j, lane, acc);
 }
 
 // dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col], t < NNB
@@ -354,10 +369,13 @@ __device__ __forceinline__ void store_fwd(float* buf, int S, const v4f (&a)[NCB]
 
 // add the bias to the value-channel column blocks
 template <int NCB, int NPB>
-__device__ __forceinline__ void add_bias(v4f (&a)[NCB], const float* __restrict__ b, int w, int g) {
-  const v4f bv = ldg4(b + 16 * w + 4 * g);
+__device__ __forceinline__ void add_bias_v(v4f (&a)[NCB], const v4f bv) {
 #pragma unroll
   for (int pb = 0; pb < NPB; ++pb) a[pb] += bv;
+}
+template <int NCB, int NPB>
+__device__ __forceinline__ void add_bias(v4f (&a)[NCB], const float* __restrict__ b, int w, int g) {
+  add_bias_v<NCB, NPB>(a, ldg4(b + 16 * w + 4 * g));
 }
 
 // output layer: ys[o][col] = W_{H+1}[o] . h[col] (+ b_{H+1}[o] on value columns)
@@ -465,6 +483,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   const int S = L.S, S2 = L.S2;
 
   float* stash_w = args.stash + (size_t)blockIdx.x * args.stash_per_wg + (size_t)w * H * NCB * 256;
+  const uint32_t lo16 = (uint32_t)lane * 16u;   // this lane's byte offset in a 1 KiB wave fragment
   const float nu = args.nu;
 
   // segment accumulators
@@ -530,22 +549,23 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     if (pde) input_layer<DIM, NCB, M_PDE>(acc, W1p, bp, xin, w, g, j);
     else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) stg4(stash_w + ((0 * NCB + cb) * 64 + lane) * 4, acc[cb]);
+    for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + (0 * NCB + cb) * 256, lo16, acc[cb]);
     if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
     else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
     store_fwd<NCB>(hin, S, acc, w, g, j);
+    auto wfrag = [&](int l) { return fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp; };
     __syncthreads();
 
     // ---- forward: hidden layers 2..H
     for (int l = 2; l <= H; ++l) {
-      const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
+      const float* Wf = wfrag(l);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
       gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
       if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, g);
       else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) stg4(stash_w + (((l - 1) * NCB + cb) * 64 + lane) * 4, acc[cb]);
+      for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16, acc[cb]);
       if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
       else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
       store_fwd<NCB>(hout, S, acc, w, g, j);
@@ -655,7 +675,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     v4f zs[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
-      zs[cb] = ldg4(stash_w + (((H - 1) * NCB + cb) * 64 + lane) * 4);
+      zs[cb] = ldg4u(stash_w + ((H - 1) * NCB + cb) * 256, lo16);
     {
       const int npb = pde ? MP::NPB : MV::NPB;
       if (tid < D * Wp) {
@@ -738,7 +758,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       // every wave has finished reading the LDS stacks before overwriting them
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
-        zs[cb] = ldg4(stash_w + (((l - 2) * NCB + cb) * 64 + lane) * 4);
+        zs[cb] = ldg4u(stash_w + ((l - 2) * NCB + cb) * 256, lo16);
       __syncthreads();
       store_fwd<NCB>(bufG, S, acc, w, g, j);
       // recompute h_{l-1} from z_{l-1}
@@ -755,7 +775,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           v4f old[4];
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            old[t] = (t < nnb && !first) ? ldg4(sw + ((size_t)(w * NW + nb0 + t) * 64 + lane) * 4) : zero4();
+            old[t] = (t < nnb && !first) ? ldg4u(sw + (size_t)(w * NW + nb0 + t) * 256, lo16) : zero4();
           v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
           switch (nnb) {
             case 4: gemm_dw<NCB, 4>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
@@ -765,14 +785,14 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           }
 #pragma unroll
           for (int t = 0; t < 4; ++t)
-            if (t < nnb) stg4(sw + ((size_t)(w * NW + nb0 + t) * 64 + lane) * 4, old[t] + dw[t]);
+            if (t < nnb) stg4u(sw + (size_t)(w * NW + nb0 + t) * 256, lo16, old[t] + dw[t]);
         }
       }
       // Hbar_{l-1} = W_l^T Zbar_l
       {
-        const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+        const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
         gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc);
       }
     }
