@@ -260,15 +260,15 @@ __device__ __forceinline__ void mfma_step(const v4f a, const float* bb, int S, i
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[q], b[cb][q], acc[cb]);
 }
 
-// a0 = this wave's first weight fragment, ldg4u(afrag, 16 * lane), issued by
-// the caller ahead of time so that its latency is not exposed at the start
 template <int NCB>
-__device__ __forceinline__ void gemm_rows_a0(const float* __restrict__ afrag, v4f a0, const float* bufB,
-                                             int S, int K4, int g, int j, int lane, v4f (&acc)[NCB]) {
+__device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const float* bufB,
+                                          int S, int K4, int g, int j, int lane,
+                                          v4f (&acc)[NCB]) {
   const float* bb = bufB + j * S + g * (4 * K4);
   const uint32_t lo = (uint32_t)lane * 16u;
   // two weight-fragment registers: the fragment of the next step is in
   // flight while the MFMAs of the current step run
+  v4f a0 = ldg4u(afrag, lo);
   int s4 = 0;
   for (; s4 + 2 <= K4; s4 += 2) {
     const v4f a1 = ldg4u(afrag + (s4 + 1) * 256, lo);
@@ -277,13 +277,6 @@ __device__ __forceinline__ void gemm_rows_a0(const float* __restrict__ afrag, v4
     mfma_step<NCB>(a1, bb, S, s4 + 1, acc);
   }
   if (s4 < K4) mfma_step<NCB>(a0, bb, S, s4, acc);
-}
-
-template <int NCB>
-__device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const float* bufB,
-                                          int S, int K4, int g, int j, int lane,
-                                          v4f (&acc)[NCB]) {
-  gemm_rows_a0<NCB>(afrag, ldg4u(afrag, (uint32_t)lane * 16u), bufB, S, K4, g, j, lane, acc);
 }
 
 // dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col], t < NNB
@@ -369,13 +362,10 @@ __device__ __forceinline__ void store_fwd(float* buf, int S, const v4f (&a)[NCB]
 
 // add the bias to the value-channel column blocks
 template <int NCB, int NPB>
-__device__ __forceinline__ void add_bias_v(v4f (&a)[NCB], const v4f bv) {
+__device__ __forceinline__ void add_bias(v4f (&a)[NCB], const float* __restrict__ b, int w, int g) {
+  const v4f bv = ldg4(b + 16 * w + 4 * g);
 #pragma unroll
   for (int pb = 0; pb < NPB; ++pb) a[pb] += bv;
-}
-template <int NCB, int NPB>
-__device__ __forceinline__ void add_bias(v4f (&a)[NCB], const float* __restrict__ b, int w, int g) {
-  add_bias_v<NCB, NPB>(a, ldg4(b + 16 * w + 4 * g));
 }
 
 // output layer: ys[o][col] = W_{H+1}[o] . h[col] (+ b_{H+1}[o] on value columns)
@@ -553,12 +543,11 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
     else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
     store_fwd<NCB>(hin, S, acc, w, g, j);
-    auto wfrag = [&](int l) { return fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp; };
     __syncthreads();
 
     // ---- forward: hidden layers 2..H
     for (int l = 2; l <= H; ++l) {
-      const float* Wf = wfrag(l);
+      const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
       gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
