@@ -212,6 +212,10 @@ def main():
     ap.add_argument("--query-seconds", type=float, default=8.0)
     ap.add_argument("--no-query", action="store_true")
     ap.add_argument("--no-eval", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="time every launch shape (points per tile, workgroups per CU) first and "
+                         "use the fastest; --tune-out FILE records it in a tuning table")
+    ap.add_argument("--tune-out", default=None)
     ap.add_argument("--per-subdomain", action="store_true",
                     help="also time one plain launch per subdomain (grouped vs plain)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -239,7 +243,21 @@ def main():
     pb = make_problem(args.workload, args.seed)
     flops, fc = step_flops(pb)
     n_pde = pb.n_pde
-    ctx = P.context_from_problem(pb, device="cuda:0", graph=True, tile_points=args.tile_points)
+    from paper_2602_15883_amd import tune
+    key = tune.tune_key(pb.dim, pb.width, pb.depth, len(pb.subs), n_pde, pb.activation)
+    if args.tile_points:
+        shape, shape_src = {"tile_points": args.tile_points}, "command line"
+    elif args.tune:
+        shape = tune.autotune(lambda **c: P.context_from_problem(pb, device="cuda:0", graph=False, **c),
+                              pb.dim, pb.width, pb.depth, len(pb.subs), n_pde, steps=3,
+                              cache=args.tune_out is not None, force=True, path=args.tune_out,
+                              activation=pb.activation)
+        shape_src = "tuned now"
+    else:
+        e = tune.lookup(key)
+        shape = {"tile_points": e["tile_points"], "blocks_per_cu": e["blocks_per_cu"]} if e else {}
+        shape_src = "tuning table" if e else "library default"
+    ctx = P.context_from_problem(pb, device="cuda:0", graph=True, **shape)
     info = ctx.launch_info()
     stream = torch.cuda.current_stream()
 
@@ -312,6 +330,7 @@ def main():
                    "n_value_points": int(sum(s.obs_x.shape[0] + s.gh_x.shape[0] + s.anc_x.shape[0]
                                              for s in pb.subs)),
                    "gflop_per_step": flops / 1e9, "tile_points": info["tile_points"],
+                   "launch_shape": shape_src,
                    "activation": pb.activation,
                    "workgroups": info["n_wg"], "graph": True, "losses_finite": finite},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA_TFLOPS,

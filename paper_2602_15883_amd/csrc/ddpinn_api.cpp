@@ -94,23 +94,54 @@ struct Partition {
   int n_wg = 0, n_seg = 0;
 };
 
-// Tiles of one subdomain, collocation tiles first, then value tiles over
-// the concatenated [observation | ghost | anchor] list.
+// Tiles of one subdomain: collocation tiles, and value tiles over the
+// concatenated [observation | ghost | anchor] list, the value tiles spread
+// evenly among the collocation tiles.  A value tile costs more than a
+// collocation tile (an activation per column instead of per point), so
+// spreading them keeps every workgroup's mix, and time, the same.
 void tiles_of(const pinn_subdomain& s, int sub, int tp, int tv, std::vector<Item>& out) {
-  for (int64_t st = 0; st < s.n_pde; st += tp)
-    out.push_back(Item{sub, ITEM_PDE, (int32_t)st, (int32_t)std::min<int64_t>(tp, s.n_pde - st), -1, 0, {0, 0}});
+  const int64_t np = (s.n_pde + tp - 1) / tp;
   const int64_t nv = s.n_obs + s.n_gh + s.n_anc;
-  for (int64_t st = 0; st < nv; st += tv)
-    out.push_back(Item{sub, ITEM_VALUE, (int32_t)st, (int32_t)std::min<int64_t>(tv, nv - st), -1, 0, {0, 0}});
+  const int64_t nvt = (nv + tv - 1) / tv;
+  int64_t ip = 0, iv = 0;
+  for (int64_t k = 0; k < np + nvt; ++k) {
+    // value tile iv goes at position floor((iv + 1/2) (np + nvt) / nvt)
+    const bool value = iv < nvt && (ip >= np || 2 * k + 1 >= (2 * iv + 1) * (np + nvt) / nvt);
+    if (value) {
+      const int64_t st = iv * tv;
+      out.push_back(Item{sub, ITEM_VALUE, (int32_t)st, (int32_t)std::min<int64_t>(tv, nv - st), -1, 0, {0, 0}});
+      ++iv;
+    } else {
+      const int64_t st = ip * tp;
+      out.push_back(Item{sub, ITEM_PDE, (int32_t)st, (int32_t)std::min<int64_t>(tp, s.n_pde - st), -1, 0, {0, 0}});
+      ++ip;
+    }
+  }
 }
 
-// Split a sorted item list into n_wg contiguous ranges and mark segments
-// (maximal runs of one subdomain inside one workgroup); slabs are numbered
-// from slab0.
-void partition(std::vector<Item>& items, int n_wg, int slab0, std::vector<int32_t>& wg_begin, int* n_seg) {
+// Relative cost of a value tile: the GEMM work of both kinds is the same,
+// the extra activation work of a value tile is per wave (independent of the
+// width) while the GEMM work per wave grows with it.
+double value_tile_cost(const Shape& sh) { return 1.0 + 21.0 / sh.Wp; }
+
+// Split a sorted item list into n_wg contiguous ranges of equal estimated
+// cost and mark segments (maximal runs of one subdomain inside one
+// workgroup); slabs are numbered from slab0.
+void partition(std::vector<Item>& items, int n_wg, double vcost, int slab0, std::vector<int32_t>& wg_begin,
+               int* n_seg) {
   const int64_t n = (int64_t)items.size();
+  std::vector<double> cum(n + 1, 0.0);
+  for (int64_t i = 0; i < n; ++i) cum[i + 1] = cum[i] + (items[i].kind == ITEM_VALUE ? vcost : 1.0);
   wg_begin.assign(n_wg + 1, 0);
-  for (int b = 0; b <= n_wg; ++b) wg_begin[b] = (int32_t)(n * b / n_wg);
+  wg_begin[n_wg] = (int32_t)n;
+  int64_t i = 0;
+  for (int b = 1; b < n_wg; ++b) {
+    const double target = cum[n] * b / n_wg;
+    while (i < n && cum[i] + 0.5 * (cum[i + 1] - cum[i]) < target) ++i;
+    // every workgroup keeps at least one item when there are enough
+    const int64_t lo = wg_begin[b - 1] + 1, hi = n - (n_wg - b);
+    wg_begin[b] = (int32_t)std::max<int64_t>(std::min<int64_t>(std::max<int64_t>(i, lo), hi), wg_begin[b - 1]);
+  }
   int seg = slab0 - 1;
   for (int b = 0; b < n_wg; ++b) {
     for (int i = wg_begin[b]; i < wg_begin[b + 1]; ++i) {
@@ -336,7 +367,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   const int max_wg = c->num_cu * c->step_occ;
   c->n_wg = std::max(1, std::min(c->n_items, max_wg));
   std::vector<int32_t> wg_begin;
-  partition(items, c->n_wg, 0, wg_begin, &c->n_seg);
+  partition(items, c->n_wg, value_tile_cost(sh), 0, wg_begin, &c->n_seg);
   // segments are numbered in item order, which is sorted by subdomain, so
   // each subdomain owns a contiguous slab range
   std::vector<int32_t> seg_begin(c->n_sub + 1, 0);
@@ -357,7 +388,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
       const int nw = std::max(1, std::min((int)its.size(), max_wg));
       std::vector<int32_t> wb;
       int nseg = 0;
-      partition(its, nw, slab0, wb, &nseg);
+      partition(its, nw, value_tile_cost(sh), slab0, wb, &nseg);
       c->ps_wg[s] = nw;
       c->ps_wgb_off[s] = (int)wgb_ps.size();
       const int base = (int)items_ps.size();

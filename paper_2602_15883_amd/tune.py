@@ -5,7 +5,9 @@ four waves) and persistent workgroups per compute unit.  Each candidate is a
 fresh context over the same device tensors; its fused-kernel time is measured
 with HIP events (PINN_TIME_KERNEL) over a few steps without the Adam update.
 Winners are cached in JSON keyed by (arch, dim, width, depth, subdomain
-count, log2 of the collocation point count).  Lookup order: the user cache
+count, log2 of the collocation point count, activation).  Candidates that the
+library maps to the same launch (points per tile, workgroup count) are timed
+once.  Lookup order: the user cache
 (DDPINN_TUNE_CACHE or ~/.cache/ddpinn/tune.json), then the table shipped with
 the package (tuned.json), else the library defaults.
 """
@@ -36,9 +38,9 @@ def arch_name() -> str:
         return "unknown"
 
 
-def tune_key(dim, width, depth, n_sub, n_pde) -> str:
+def tune_key(dim, width, depth, n_sub, n_pde, activation: str = "tanh") -> str:
     b = int(math.floor(math.log2(max(n_pde, 1))))
-    return f"{arch_name()}|d{dim}|w{width}|h{depth}|s{n_sub}|n2^{b}"
+    return f"{arch_name()}|d{dim}|w{width}|h{depth}|s{n_sub}|n2^{b}|{activation}"
 
 
 def _load(path) -> Dict:
@@ -79,37 +81,54 @@ def candidates(width: int) -> List[dict]:
     return out
 
 
-def measure(make_ctx, cand: dict, steps: int = 3, warmup: int = 1) -> float:
-    """Average fused-kernel milliseconds of one candidate (no Adam update)."""
+def measure(make_ctx, cand: dict, steps: int = 3, warmup: int = 1, seen: Optional[dict] = None) -> float:
+    """Average fused-kernel milliseconds of one candidate (no Adam update).
+    Candidates whose launch (points per tile, workgroup count) equals one in
+    `seen` are not timed again."""
     ctx: Context = make_ctx(**cand)
     try:
         info = ctx.launch_info()
         if info["tile_points"] != cand["tile_points"]:
             return float("inf")
+        launch = (info["tile_points"], info["n_wg"])
+        if seen is not None and launch in seen:
+            return seen[launch]
         for _ in range(warmup):
             ctx.step(1, update=False, time_kernel=True)
         ctx.kernel_time()
         for _ in range(steps):
             ctx.step(1, update=False, time_kernel=True)
         ms, n = ctx.kernel_time()
-        return ms / max(n, 1)
+        ms /= max(n, 1)
+        if seen is not None:
+            seen[launch] = ms
+        return ms
     finally:
         ctx.close()
 
 
 def autotune(make_ctx, dim, width, depth, n_sub, n_pde, steps: int = 3,
-             cache: bool = True, force: bool = False, verbose: bool = False) -> dict:
+             cache: bool = True, force: bool = False, verbose: bool = False,
+             path: Optional[str] = None, activation: str = "tanh") -> dict:
     """Return the best {tile_points, blocks_per_cu} for this shape, from the
-    caches or by timing every candidate.  make_ctx(**cand) builds a Context."""
-    key = tune_key(dim, width, depth, n_sub, n_pde)
+    caches or by timing every candidate.  make_ctx(**cand) builds a Context.
+    With cache, the winner and every trial are stored in `path` (default: the
+    user cache)."""
+    key = tune_key(dim, width, depth, n_sub, n_pde, activation)
     if not force:
         e = lookup(key)
         if e:
             return {"tile_points": e["tile_points"], "blocks_per_cu": e["blocks_per_cu"]}
     best, best_ms, trials = None, float("inf"), []
-    for cand in candidates(width):
+    seen: dict = {}
+    cands = candidates(width)
+    try:   # one untimed pass first: the first launch of a process pays start-up costs
+        measure(make_ctx, cands[0], steps=1)
+    except Exception:
+        pass
+    for cand in cands:
         try:
-            ms = measure(make_ctx, cand, steps=steps)
+            ms = measure(make_ctx, cand, steps=steps, seen=seen)
         except Exception as ex:  # a candidate the library rejects
             if verbose:
                 print("tune: skip", cand, ex)
@@ -122,5 +141,5 @@ def autotune(make_ctx, dim, width, depth, n_sub, n_pde, steps: int = 3,
     if best is None:
         raise RuntimeError("no launch candidate worked")
     if cache:
-        store(key, {**best, "ms": best_ms, "trials": trials})
+        store(key, {**best, "ms": best_ms, "trials": trials}, path=path)
     return dict(best)
