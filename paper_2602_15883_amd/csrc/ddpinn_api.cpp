@@ -87,13 +87,6 @@ Shape make_shape(int dim, int W, int H) {
   return sh;
 }
 
-struct Partition {
-  std::vector<Item> items;
-  std::vector<int32_t> wg_begin;   // n_wg + 1
-  std::vector<int32_t> seg_begin;  // n_sub + 1
-  int n_wg = 0, n_seg = 0;
-};
-
 // Tiles of one subdomain: collocation tiles, and value tiles over the
 // concatenated [observation | ghost | anchor] list, the value tiles spread
 // evenly among the collocation tiles.  A value tile costs more than a
@@ -167,10 +160,12 @@ struct pinn_ctx {
   int threads = 0;
   int lds_floats = 0, qlds_floats = 0;
   int step_occ = 1, query_occ = 1;
-  // grouped launch
-  int n_wg = 0, n_items = 0, n_seg = 0;
+  // grouped launch: n_wg workgroups over n_ranges item ranges (taken in
+  // turn through a counter when several workgroups share a compute unit)
+  int n_wg = 0, n_ranges = 0, n_items = 0, n_seg = 0;
+  bool dynamic = false;
   // per-subdomain launches
-  std::vector<int> ps_wg, ps_wgb_off;
+  std::vector<int> ps_wg, ps_nr, ps_wgb_off;
   int ps_items = 0, ps_seg = 0;
   int n_slabs = 0, n_chunks = 1;
   int64_t stash_per_wg = 0;
@@ -178,6 +173,7 @@ struct pinn_ctx {
   SubDev* d_subs = nullptr;
   Item* d_items = nullptr;
   int32_t* d_wg_begin = nullptr;
+  int32_t* d_counters = nullptr;   // [1 + n_sub]: grouped launch, then each plain launch
   int32_t* d_seg_begin = nullptr;
   Item* d_items_ps = nullptr;
   int32_t* d_wgb_ps = nullptr;
@@ -366,8 +362,15 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->n_items = (int)items.size();
   const int max_wg = c->num_cu * c->step_occ;
   c->n_wg = std::max(1, std::min(c->n_items, max_wg));
+  // With several workgroups per compute unit the co-resident ones advance at
+  // different rates; ranges handed out in turn (four per workgroup) even it out.
+  c->dynamic = c->step_occ > 1;
+  auto ranges_for = [&](int n_items, int n_wg) {
+    return c->dynamic ? std::max(1, std::min(n_items, 4 * n_wg)) : n_wg;
+  };
+  c->n_ranges = ranges_for(c->n_items, c->n_wg);
   std::vector<int32_t> wg_begin;
-  partition(items, c->n_wg, value_tile_cost(sh), 0, wg_begin, &c->n_seg);
+  partition(items, c->n_ranges, value_tile_cost(sh), 0, wg_begin, &c->n_seg);
   // segments are numbered in item order, which is sorted by subdomain, so
   // each subdomain owns a contiguous slab range
   std::vector<int32_t> seg_begin(c->n_sub + 1, 0);
@@ -377,6 +380,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   std::vector<Item> items_ps;
   std::vector<int32_t> wgb_ps, seg_ps(c->n_sub + 1, 0);
   c->ps_wg.assign(c->n_sub, 0);
+  c->ps_nr.assign(c->n_sub, 0);
   c->ps_wgb_off.assign(c->n_sub, 0);
   {
     int slab0 = 0;
@@ -386,10 +390,12 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
       seg_ps[s] = slab0;
       if (its.empty()) continue;
       const int nw = std::max(1, std::min((int)its.size(), max_wg));
+      const int nr = ranges_for((int)its.size(), nw);
       std::vector<int32_t> wb;
       int nseg = 0;
-      partition(its, nw, value_tile_cost(sh), slab0, wb, &nseg);
+      partition(its, nr, value_tile_cost(sh), slab0, wb, &nseg);
       c->ps_wg[s] = nw;
+      c->ps_nr[s] = nr;
       c->ps_wgb_off[s] = (int)wgb_ps.size();
       const int base = (int)items_ps.size();
       for (int32_t v : wb) wgb_ps.push_back(v + base);
@@ -423,7 +429,8 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
   const size_t o_subs = take(sizeof(SubDev) * c->n_sub);
   const size_t o_items = take(sizeof(Item) * std::max(c->n_items, 1));
-  const size_t o_wgb = take(sizeof(int32_t) * (c->n_wg + 1));
+  const size_t o_wgb = take(sizeof(int32_t) * (c->n_ranges + 1));
+  const size_t o_counters = take(sizeof(int32_t) * (1 + c->n_sub));
   const size_t o_segb = take(sizeof(int32_t) * (c->n_sub + 1));
   const size_t o_items_ps = take(sizeof(Item) * std::max(c->ps_items, 1));
   const size_t o_wgb_ps = take(sizeof(int32_t) * std::max<size_t>(wgb_ps.size(), 1));
@@ -452,6 +459,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->d_subs = (SubDev*)(ws + o_subs);
   c->d_items = (Item*)(ws + o_items);
   c->d_wg_begin = (int32_t*)(ws + o_wgb);
+  c->d_counters = (int32_t*)(ws + o_counters);
   c->d_seg_begin = (int32_t*)(ws + o_segb);
   c->d_items_ps = (Item*)(ws + o_items_ps);
   c->d_wgb_ps = (int32_t*)(ws + o_wgb_ps);
@@ -513,7 +521,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(hipMemcpyAsync(c->d_subs, sd.data(), sizeof(SubDev) * c->n_sub, hipMemcpyHostToDevice, s));
   if (c->n_items) HIPCHECK(hipMemcpyAsync(c->d_items, items.data(), sizeof(Item) * c->n_items, hipMemcpyHostToDevice, s));
-  HIPCHECK(hipMemcpyAsync(c->d_wg_begin, wg_begin.data(), sizeof(int32_t) * (c->n_wg + 1), hipMemcpyHostToDevice, s));
+  HIPCHECK(hipMemcpyAsync(c->d_wg_begin, wg_begin.data(), sizeof(int32_t) * (c->n_ranges + 1), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(c->d_seg_begin, seg_begin.data(), sizeof(int32_t) * (c->n_sub + 1), hipMemcpyHostToDevice, s));
   if (c->ps_items) HIPCHECK(hipMemcpyAsync(c->d_items_ps, items_ps.data(), sizeof(Item) * c->ps_items, hipMemcpyHostToDevice, s));
   if (!wgb_ps.empty()) HIPCHECK(hipMemcpyAsync(c->d_wgb_ps, wgb_ps.data(), sizeof(int32_t) * wgb_ps.size(), hipMemcpyHostToDevice, s));
@@ -524,10 +532,14 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->pargs.sh = sh;
   c->pargs.subs = c->d_subs;
   c->pargs.n_sub = c->n_sub;
+  c->pargs.counters = c->d_counters;
+  c->pargs.n_counters = 1 + c->n_sub;
   c->sargs.sh = sh;
   c->sargs.subs = c->d_subs;
   c->sargs.items = c->d_items;
   c->sargs.wg_begin = c->d_wg_begin;
+  c->sargs.counter = c->dynamic ? c->d_counters : nullptr;
+  c->sargs.n_ranges = c->n_ranges;
   c->sargs.slabs = c->d_slabs;
   c->sargs.stash = c->d_stash;
   c->sargs.stash_per_wg = c->stash_per_wg;
@@ -636,6 +648,8 @@ static pinn_status run_step_eager(pinn_ctx* c, bool per_sub, bool timed, hipStre
       StepArgs a = c->sargs;
       a.items = c->d_items_ps;
       a.wg_begin = c->d_wgb_ps + c->ps_wgb_off[k];
+      a.counter = c->dynamic ? c->d_counters + 1 + k : nullptr;
+      a.n_ranges = c->ps_nr[k];
       HIPCHECK(launch_step(a, c->tile_points, c->ps_wg[k], s));
     }
     ra.seg_begin = c->d_seg_ps;

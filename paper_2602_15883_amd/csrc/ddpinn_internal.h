@@ -79,7 +79,9 @@ struct StepArgs {
   Shape sh;
   const SubDev* subs;
   const Item* items;
-  const int32_t* wg_begin;  // [n_wg + 1] item range of each workgroup
+  const int32_t* wg_begin;  // [n_ranges + 1] item ranges
+  int32_t* counter;         // next free range (zeroed by prep_kernel); NULL: range = workgroup index
+  int32_t n_ranges;
   float* slabs;
   float* stash;
   int64_t stash_per_wg;     // floats
@@ -112,6 +114,8 @@ struct PrepArgs {
   Shape sh;
   const SubDev* subs;
   int32_t n_sub;
+  int32_t n_counters;
+  int32_t* counters;        // range counters of the step launches, zeroed here
 };
 
 // Query modes

@@ -418,7 +418,7 @@ __device__ __forceinline__ void residuals(F Y, float nu, float (&r)[DIM + 1]) {
 // ---------------------------------------------------------------------------
 struct StepLds {
   int S, S2, NCOL;
-  int bufH, bufG, ys, yb, xin, acc1, dbacc, red, total;
+  int bufH, bufG, ys, yb, xin, acc1, dbacc, red, sched, total;
 };
 
 __host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB) {
@@ -436,6 +436,7 @@ __host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB) {
   L.acc1 = o; o += (Wp * D + 3) & ~3;
   L.dbacc = o; o += (H * Wp + 3) & ~3;
   L.red = o;  o += 64;
+  L.sched = o; o += 4;   // the item range taken by the workgroup
   L.total = o;
   return L;
 }
@@ -480,8 +481,21 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   float lacc[6];
   float dwo = 0.f, dbo = 0.f;
 
-  const int it0 = ((const CONST_AS int32_t*)args.wg_begin)[blockIdx.x];
-  const int it1 = ((const CONST_AS int32_t*)args.wg_begin)[blockIdx.x + 1];
+  // Item ranges: range blockIdx.x, or, with a counter, ranges taken in turn
+  // until none is left (workgroups that share a compute unit do not progress
+  // at the same rate, so a static split would leave the slower one last).
+  int* s_range = reinterpret_cast<int*>(lds + L.sched);
+  int range = blockIdx.x;
+  for (;;) {
+  if (args.counter) {
+    __syncthreads();   // every thread has read the previous range index
+    if (tid == 0) *s_range = atomicAdd(args.counter, 1);
+    __syncthreads();
+    range = *s_range;
+  }
+  if (range >= args.n_ranges) break;
+  const int it0 = ((const CONST_AS int32_t*)args.wg_begin)[range];
+  const int it1 = ((const CONST_AS int32_t*)args.wg_begin)[range + 1];
   for (int it = it0; it < it1; ++it) {
     __syncthreads();   // the previous tile's readers of xin/acc1 are done
     const CONST_AS Item& ir = ((const CONST_AS Item*)args.items)[it];
@@ -811,6 +825,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       __syncthreads();
     }
   }
+  if (!args.counter) break;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -820,6 +836,7 @@ __global__ void prep_kernel(const PrepArgs a) {
   const Shape& sh = a.sh;
   const int s = blockIdx.y;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s == 0 && idx < a.n_counters) a.counters[idx] = 0;
   if (idx >= sh.frag_floats) return;
   const float* th = a.subs[s].theta;
   float* fr = a.subs[s].frag;
