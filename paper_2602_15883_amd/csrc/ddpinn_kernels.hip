@@ -564,7 +564,12 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+      // The two waves sharing a SIMD run the same GEMM; the hardware favours
+      // the older one, which then idles at the next barrier while the younger
+      // finishes.  Raising the younger half's priority for the GEMM evens them.
+      if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
       gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
+      __builtin_amdgcn_s_setprio(0);
       if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, g);
       else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
 #pragma unroll
@@ -773,6 +778,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       {
         float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
         const bool first = item.flags & ITEM_FIRST;
+        if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);   // as in the forward GEMM
         for (int nb0 = 0; nb0 < NW; nb0 += 4) {
           const int nnb = (NW - nb0) < 4 ? (NW - nb0) : 4;
           v4f old[4];
@@ -791,12 +797,15 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
             if (t < nnb) stg4u(sw + (size_t)(w * NW + nb0 + t) * 256, lo16, old[t] + dw[t]);
         }
       }
+      __builtin_amdgcn_s_setprio(0);
       // Hbar_{l-1} = W_l^T Zbar_l
       {
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
         const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
+        if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
         gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc);
+        __builtin_amdgcn_s_setprio(0);
       }
     }
 
