@@ -159,7 +159,9 @@ struct pinn_ctx {
   int tile_points = 16, value_points = 0;
   int threads = 0;
   int lds_floats = 0, qlds_floats = 0;
-  int step_occ = 1, query_occ = 1;
+  int step_occ = 1;
+  int query_occ[4] = {1, 1, 1, 1};   // resident query workgroups per compute unit, by query kind
+  int exch_occ = 1;
   // grouped launch: n_wg workgroups over n_ranges item ranges (taken in
   // turn through a counter when several workgroups share a compute unit)
   int n_wg = 0, n_ranges = 0, n_items = 0, n_seg = 0;
@@ -354,7 +356,21 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->lds_floats = step_lds_floats(sh, tp);
   c->step_occ = cfg->blocks_per_cu > 0 ? std::min(cfg->blocks_per_cu, occ) : occ;
   c->qlds_floats = query_lds_floats(sh);
-  c->query_occ = std::max(1, std::min(max_lds / std::max(1, c->qlds_floats * 4), 2048 / c->threads));
+  // resident workgroups per compute unit (registers and LDS): the query and
+  // exchange grids are persistent, so a grid larger than what is resident
+  // would leave its last workgroups to start after the others finish
+  for (int q = 0; q < 4; ++q) {
+    int nb = 0;
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, query_kernel_ptr(sh.dim, q, sh.act), c->threads,
+                                                          (size_t)c->qlds_floats * 4));
+    c->query_occ[q] = std::max(1, nb);
+  }
+  {
+    int nb = 0;
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, exchange_kernel_ptr(sh.dim, sh.act), c->threads,
+                                                          (size_t)c->qlds_floats * 4));
+    c->exch_occ = std::max(1, nb);
+  }
 
   // work items: grouped partition and per-subdomain partitions
   std::vector<Item> items;
@@ -736,7 +752,7 @@ pinn_status pinn_query(pinn_ctx* c, const float* x, int64_t n, int32_t sub, uint
   qa.lds_floats = c->qlds_floats;
   const int CF = 2 * sh.dim + 2;
   const int npts = (what == PINN_Q_VALUE) ? 16 * CF : (what == PINN_Q_UVPW ? 16 * CF / (sh.dim + 1) : 16);
-  const int max_wg = c->num_cu * c->query_occ;
+  const int max_wg = c->num_cu * c->query_occ[what];
   if (sub >= 0) {
     const int64_t tiles = (n + npts - 1) / npts;
     HIPCHECK(launch_query(qa, (int)std::min<int64_t>(tiles, max_wg), s));
@@ -818,7 +834,7 @@ pinn_status pinn_exchange(pinn_ctx* c, const pinn_face* faces, int32_t n_faces, 
   ea.lds_floats = c->qlds_floats;
   ea.targets = c->d_targets;
   for (int q = 0; q < sh.dim; ++q) ea.x_anc[q] = x_anc[q];
-  HIPCHECK(launch_exchange(ea, (int)std::min<int64_t>((int64_t)its.size(), (int64_t)c->num_cu * c->query_occ), s));
+  HIPCHECK(launch_exchange(ea, (int)std::min<int64_t>((int64_t)its.size(), (int64_t)c->num_cu * c->exch_occ), s));
   return PINN_OK;
 }
 
@@ -907,7 +923,7 @@ pinn_status pinn_evaluate(pinn_ctx* c, const float* x, const float* ref, int64_t
   qa.nu = (float)c->cfg.nu;
   qa.lds_floats = c->qlds_floats;
   const int npts = 16 * (2 * sh.dim + 2);
-  const int nwg = (int)std::min<int64_t>((n + npts - 1) / npts + c->n_sub, (int64_t)c->num_cu * c->query_occ);
+  const int nwg = (int)std::min<int64_t>((n + npts - 1) / npts + c->n_sub, (int64_t)c->num_cu * c->query_occ[Q_VALUE]);
   HIPCHECK(launch_query(qa, nwg, s));
   // p(x_anc, t) by the same network, only where that network is a master
   HIPCHECK(launch_anchor_points(x, n, D, x_anc, xa, s));

@@ -198,6 +198,8 @@ hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s);
 
 // Kernel entry points and their LDS needs (for graph nodes and occupancy).
 const void* step_kernel_ptr(int dim, int tile_points, int act);
+const void* query_kernel_ptr(int dim, int what, int act);   // what: Q_VALUE, Q_UVPW, Q_CHANNELS/Q_RESIDUAL
+const void* exchange_kernel_ptr(int dim, int act);
 const void* prep_kernel_ptr();
 const void* slab_sum_kernel_ptr();
 const void* grad_kernel_ptr();

@@ -1019,12 +1019,16 @@ __global__ void route_zero_kernel(int32_t* counts, int32_t* cursor, int n_sub) {
   for (int s = threadIdx.x; s < n_sub; s += blockDim.x) { counts[s] = 0; cursor[s] = 0; }
 }
 
-__global__ void route_count_kernel(const RouteArgs a) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+// Routing is a counting sort by subdomain.  Points are counted in a per-block
+// LDS histogram and each block adds its counts to the global ones with one
+// atomic per subdomain; the scatter reserves a contiguous slot range per
+// (block, subdomain) the same way.  (Global atomics per point serialise on
+// the few subdomain counters.)
+constexpr int kRouteBlock = 256;
+
+__device__ __forceinline__ int route_point(const RouteArgs& a, int64_t i) {
   const float* x = a.x + i * a.D;
-  int found = -1;
-  for (int s = 0; s < a.n_sub && found < 0; ++s) {
+  for (int s = 0; s < a.n_sub; ++s) {
     const float* lo = a.boxes + s * 8;
     const float* hi = lo + 4;
     bool in = true;
@@ -1033,12 +1037,26 @@ __global__ void route_count_kernel(const RouteArgs a) {
       const bool ok = (c >= lo[q]) && (c < hi[q] || (c == hi[q] && hi[q] == a.gmax[q]));
       if (!ok) { in = false; break; }
     }
-    if (in) found = s;
+    if (in) return s;
   }
-  a.sub_id[i] = found;
-  if (found >= 0) atomicAdd(a.counts + found, 1);
-  else
-    for (int q = 0; q < a.out_cols; ++q) a.out[i * a.out_cols + q] = __builtin_nanf("");
+  return -1;
+}
+
+__global__ __launch_bounds__(kRouteBlock) void route_count_kernel(const RouteArgs a) {
+  extern __shared__ int hist[];   // [n_sub]
+  for (int s = threadIdx.x; s < a.n_sub; s += blockDim.x) hist[s] = 0;
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.n) {
+    const int found = route_point(a, i);
+    a.sub_id[i] = found;
+    if (found >= 0) atomicAdd(&hist[found], 1);
+    else
+      for (int q = 0; q < a.out_cols; ++q) a.out[i * a.out_cols + q] = __builtin_nanf("");
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < a.n_sub; s += blockDim.x)
+    if (hist[s]) atomicAdd(a.counts + s, hist[s]);
 }
 
 __global__ void route_offsets_kernel(const RouteArgs a) {
@@ -1049,13 +1067,20 @@ __global__ void route_offsets_kernel(const RouteArgs a) {
   }
 }
 
-__global__ void route_scatter_kernel(const RouteArgs a) {
+__global__ __launch_bounds__(kRouteBlock) void route_scatter_kernel(const RouteArgs a) {
+  extern __shared__ int sh[];   // hist[n_sub], base[n_sub]
+  int* hist = sh;
+  int* base = sh + a.n_sub;
+  for (int s = threadIdx.x; s < a.n_sub; s += blockDim.x) hist[s] = 0;
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
-  const int s = a.sub_id[i];
-  if (s < 0) return;
-  const int slot = a.offsets[s] + atomicAdd(a.cursor + s, 1);
-  a.perm[slot] = (int32_t)i;
+  const int s = (i < a.n) ? a.sub_id[i] : -1;
+  const int rank = (s >= 0) ? atomicAdd(&hist[s], 1) : 0;
+  __syncthreads();
+  for (int q = threadIdx.x; q < a.n_sub; q += blockDim.x)
+    base[q] = hist[q] ? a.offsets[q] + atomicAdd(a.cursor + q, hist[q]) : 0;
+  __syncthreads();
+  if (s >= 0) a.perm[base[s] + rank] = (int32_t)i;
 }
 
 struct QueryLds { int S, NCOL, bufH, ys, xin, pidx, total; };
@@ -1121,7 +1146,18 @@ __global__ __launch_bounds__(512) void query_kernel(const QueryArgs a) {
     const int64_t c = a.counts ? a.counts[s] : a.n;
     total += (c + NPTS - 1) / NPTS;
   }
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+  // Tiles are ordered by subdomain.  Workgroups are dispatched to the eight
+  // XCDs round-robin (workgroup b on XCD b mod 8), each XCD with its own L2:
+  // with a grid that is a multiple of 8, XCD x takes the x-th eighth of the
+  // tiles, so each L2 holds the weights of a few subdomains, not all.
+  int64_t t0 = blockIdx.x, tend = total, tstep = gridDim.x;
+  if (gridDim.x >= 16 && (gridDim.x & 7) == 0) {
+    const int64_t x = blockIdx.x & 7;
+    t0 = x * total / 8 + (blockIdx.x >> 3);
+    tend = (x + 1) * total / 8;
+    tstep = gridDim.x >> 3;
+  }
+  for (int64_t t = t0; t < tend; t += tstep) {
     int s = 0;
     int64_t tl = t, c = 0;
     for (; s < nsub; ++s) {
@@ -1429,10 +1465,11 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 
 hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(route_zero_kernel, dim3(1), dim3(256), 0, s, a.counts, a.cursor, a.n_sub);
-  const unsigned nb = (unsigned)((a.n + 255) / 256);
-  if (nb) hipLaunchKernelGGL(route_count_kernel, dim3(nb), dim3(256), 0, s, a);
+  const unsigned nb = (unsigned)((a.n + kRouteBlock - 1) / kRouteBlock);
+  const size_t h = sizeof(int) * (size_t)a.n_sub;
+  if (nb) hipLaunchKernelGGL(route_count_kernel, dim3(nb), dim3(kRouteBlock), h, s, a);
   hipLaunchKernelGGL(route_offsets_kernel, dim3(1), dim3(64), 0, s, a);
-  if (nb) hipLaunchKernelGGL(route_scatter_kernel, dim3(nb), dim3(256), 0, s, a);
+  if (nb) hipLaunchKernelGGL(route_scatter_kernel, dim3(nb), dim3(kRouteBlock), 2 * h, s, a);
   return hipGetLastError();
 }
 
@@ -1441,28 +1478,31 @@ static const void* query_ptr_act(int act) {
   return act == ACT_SIN ? (const void*)query_kernel<DIM, MODE, ACT_SIN> : (const void*)query_kernel<DIM, MODE, ACT_TANH>;
 }
 
+const void* query_kernel_ptr(int dim, int what, int act) {
+  const int mode = (what == Q_VALUE) ? M_VALUE : (what == Q_UVPW ? M_GRAD : M_PDE);
+  if (dim == 2)
+    return mode == M_VALUE ? query_ptr_act<2, M_VALUE>(act) : (mode == M_GRAD ? query_ptr_act<2, M_GRAD>(act) : query_ptr_act<2, M_PDE>(act));
+  return mode == M_VALUE ? query_ptr_act<3, M_VALUE>(act) : (mode == M_GRAD ? query_ptr_act<3, M_GRAD>(act) : query_ptr_act<3, M_PDE>(act));
+}
+
+const void* exchange_kernel_ptr(int dim, int act) {
+  if (dim == 2) return act == ACT_SIN ? (const void*)exchange_kernel<2, ACT_SIN> : (const void*)exchange_kernel<2, ACT_TANH>;
+  return act == ACT_SIN ? (const void*)exchange_kernel<3, ACT_SIN> : (const void*)exchange_kernel<3, ACT_TANH>;
+}
+
 hipError_t launch_query(const QueryArgs& a, int n_wg, hipStream_t s) {
+  if (n_wg >= 16) n_wg &= ~7;   // a multiple of the XCD count (see query_kernel)
   const size_t lds = (size_t)a.lds_floats * sizeof(float);
   const dim3 block(a.sh.NW * 64);
-  const int mode = (a.what == Q_VALUE) ? M_VALUE : (a.what == Q_UVPW ? M_GRAD : M_PDE);
-  const int act = a.sh.act;
-  const void* k;
-  if (a.sh.dim == 2)
-    k = mode == M_VALUE ? query_ptr_act<2, M_VALUE>(act) : (mode == M_GRAD ? query_ptr_act<2, M_GRAD>(act) : query_ptr_act<2, M_PDE>(act));
-  else
-    k = mode == M_VALUE ? query_ptr_act<3, M_VALUE>(act) : (mode == M_GRAD ? query_ptr_act<3, M_GRAD>(act) : query_ptr_act<3, M_PDE>(act));
   void* args[] = {const_cast<QueryArgs*>(&a)};
-  return hipLaunchKernel(k, dim3(n_wg), block, args, lds, s);
+  return hipLaunchKernel(query_kernel_ptr(a.sh.dim, a.what, a.sh.act), dim3(n_wg), block, args, lds, s);
 }
 
 hipError_t launch_exchange(const ExchangeArgs& a, int n_wg, hipStream_t s) {
   const size_t lds = (size_t)a.lds_floats * sizeof(float);
   const dim3 block(a.sh.NW * 64);
-  const void* k;
-  if (a.sh.dim == 2) k = a.sh.act == ACT_SIN ? (const void*)exchange_kernel<2, ACT_SIN> : (const void*)exchange_kernel<2, ACT_TANH>;
-  else k = a.sh.act == ACT_SIN ? (const void*)exchange_kernel<3, ACT_SIN> : (const void*)exchange_kernel<3, ACT_TANH>;
   void* args[] = {const_cast<ExchangeArgs*>(&a)};
-  return hipLaunchKernel(k, dim3(n_wg), block, args, lds, s);
+  return hipLaunchKernel(exchange_kernel_ptr(a.sh.dim, a.sh.act), dim3(n_wg), block, args, lds, s);
 }
 
 // LDS above 64 KiB must be allowed per kernel before launch.
