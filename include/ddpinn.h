@@ -4,7 +4,7 @@
  *
  * One context holds one or more subdomain networks ("local experts",
  * section 2.2) of the same architecture: a fully connected tanh MLP
- * (x_1..x_d, t) -> (u_1..u_d, p) with H hidden layers of width W <= 128
+ * (x_1..x_d, t) -> (u_1..u_d, p) with H hidden layers of width W <= 256 (see pinn_config.width)
  * (section 2.1, network equation).  A training step evaluates, for every
  * subdomain at once in one grouped launch,
  *
@@ -80,7 +80,11 @@ typedef enum {
 
 typedef struct {
   int32_t dim;            /* 2 or 3 spatial dimensions                        */
-  int32_t width;          /* W, 1..128                                        */
+  int32_t width;          /* W, 1..256.  Above 128 each wave of a workgroup
+                             owns two 16-neuron row blocks.  A collocation
+                             tile must fit in LDS, else PINN_E_UNSUPPORTED:
+                             2D up to 176 at any depth (192 to depth 6), 3D up
+                             to 128 (144 to depth 5)                         */
   int32_t depth;          /* H hidden layers, 1..16                           */
   int32_t n_sub;          /* number of subdomains, 1..4096                    */
   int32_t activation;     /* 0 = tanh, 1 = sin (the paper's cylinder networks) */

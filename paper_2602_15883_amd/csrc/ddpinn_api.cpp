@@ -56,6 +56,7 @@ Shape make_shape(int dim, int W, int H) {
   sh.H = H;
   sh.Wp = (W + 15) / 16 * 16;
   sh.NW = sh.Wp / 16;
+  sh.NWV = std::min(sh.NW, kMaxWaves);
   sh.P = (int32_t)nparams(dim, W, H);
   const int64_t Wp = sh.Wp, D = sh.D;
   // packed offsets
@@ -334,13 +335,14 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
 
   // tile shape: 32-point collocation tiles when they fit in LDS with at
   // least the occupancy of 16-point tiles, unless fixed by the caller
-  c->threads = sh.NW * 64;
+  c->threads = sh.NWV * 64;
   auto occ_of = [&](int tp, int* occ) -> pinn_status {
     const int lf = step_lds_floats(sh, tp);
+    const void* k = step_kernel_ptr(sh, tp);
     // 32-point tiles hold twice the registers: at most 4 waves (Wp <= 64)
-    if ((int64_t)lf * 4 > max_lds || (tp == 32 && c->threads > 256)) { *occ = 0; return PINN_OK; }
+    if (!k || (int64_t)lf * 4 > max_lds || (tp == 32 && c->threads > 256)) { *occ = 0; return PINN_OK; }
     int nb = 0;
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel_ptr(sh.dim, tp, sh.act), c->threads, (size_t)lf * 4));
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, c->threads, (size_t)lf * 4));
     *occ = nb;
     return PINN_OK;
   };
@@ -350,7 +352,12 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   int tp = cfg->tile_points;
   if (tp == 0) tp = 16;
   const int occ = (tp == 32) ? occ32 : occ16;
-  if (occ < 1) return fail(PINN_E_UNSUPPORTED, "tile of %d points does not fit (LDS %d B)", tp, step_lds_floats(sh, tp) * 4);
+  if (occ < 1) {
+    if (!step_kernel_ptr(sh, tp))
+      return fail(PINN_E_UNSUPPORTED, "width %d: only 16-point tiles above %d neurons", cfg->width, 16 * kMaxWaves);
+    return fail(PINN_E_UNSUPPORTED, "tile of %d points needs %d B of LDS per workgroup (device limit %d B)", tp,
+                step_lds_floats(sh, tp) * 4, max_lds);
+  }
   c->tile_points = tp;
   c->value_points = step_value_points(sh.dim, tp);
   c->lds_floats = step_lds_floats(sh, tp);
@@ -361,13 +368,13 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   // would leave its last workgroups to start after the others finish
   for (int q = 0; q < 4; ++q) {
     int nb = 0;
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, query_kernel_ptr(sh.dim, q, sh.act), c->threads,
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, query_kernel_ptr(sh, q), c->threads,
                                                           (size_t)c->qlds_floats * 4));
     c->query_occ[q] = std::max(1, nb);
   }
   {
     int nb = 0;
-    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, exchange_kernel_ptr(sh.dim, sh.act), c->threads,
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, exchange_kernel_ptr(sh), c->threads,
                                                           (size_t)c->qlds_floats * 4));
     c->exch_occ = std::max(1, nb);
   }
@@ -593,7 +600,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
     HIPCHECK(hipGraphAddKernelNode(&n1, gr, nullptr, 0, &kp));
     void* sa[] = {&c->sargs};
     hipKernelNodeParams ks{};
-    ks.func = (void*)step_kernel_ptr(sh.dim, c->tile_points, sh.act);
+    ks.func = (void*)step_kernel_ptr(sh, c->tile_points);
     ks.gridDim = dim3(c->n_wg);
     ks.blockDim = dim3(c->threads);
     ks.sharedMemBytes = (unsigned)(c->lds_floats * 4);

@@ -7,7 +7,8 @@
 namespace ddp {
 
 constexpr int kWave = 64;
-constexpr int kMaxWidth = 128;
+constexpr int kMaxWidth = 256;
+constexpr int kMaxWaves = 8;    // waves per workgroup of the network kernels
 constexpr int kMaxDepth = 16;
 constexpr int kMaxSub = 4096;
 constexpr int kSlabChunk = 16;   // slabs summed per thread in the first reduce stage
@@ -51,9 +52,12 @@ struct Item {
 // Geometry of one network and of the buffers derived from it.  Offsets are
 // in floats.
 struct Shape {
-  int32_t dim, D, W, H, Wp, NW;   // D = dim+1 inputs/outputs; Wp = W padded to 16; NW = Wp/16
+  int32_t dim, D, W, H, Wp, NW;   // D = dim+1 inputs/outputs; Wp = W padded to 16; NW = Wp/16 row blocks
   int32_t P;                      // packed parameter count
   int32_t act;                    // activation: 0 tanh, 1 sin
+  int32_t NWV;                    // waves per workgroup, min(NW, kMaxWaves): wave w owns row
+                                  // block w and, when NW > kMaxWaves, row block w + NWV
+  int32_t pad_;
   // fragment buffer (per subdomain)
   int64_t f_hid;   // hidden layer l (2..H): forward A-fragments at f_hid + (l-2)*2*Wp*Wp,
                    // transposed (backward) A-fragments Wp*Wp further
@@ -197,9 +201,9 @@ hipError_t launch_master_counts(const SubDev* subs, const int32_t* counts, int n
 hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s);
 
 // Kernel entry points and their LDS needs (for graph nodes and occupancy).
-const void* step_kernel_ptr(int dim, int tile_points, int act);
-const void* query_kernel_ptr(int dim, int what, int act);   // what: Q_VALUE, Q_UVPW, Q_CHANNELS/Q_RESIDUAL
-const void* exchange_kernel_ptr(int dim, int act);
+const void* step_kernel_ptr(const Shape& sh, int tile_points);
+const void* query_kernel_ptr(const Shape& sh, int what);   // what: Q_VALUE, Q_UVPW, Q_CHANNELS/Q_RESIDUAL
+const void* exchange_kernel_ptr(const Shape& sh);
 const void* prep_kernel_ptr();
 const void* slab_sum_kernel_ptr();
 const void* grad_kernel_ptr();

@@ -12,8 +12,11 @@
 //   A tile holds NCB column blocks of 16 columns.  A collocation tile has
 //   16*PBP points and one column block per (channel, 16 points); a value tile
 //   (observation, ghost or anchor points, value channel only) has 16*NCB
-//   points.  A workgroup of Wp/16 waves processes one tile at a time; wave w
-//   owns neurons [16w, 16w+16) of every layer.
+//   points.  A workgroup of min(Wp/16, 8) waves processes one tile at a
+//   time; wave w owns the row block of neurons [16w, 16w+16) of every layer
+//   and, for widths above 128 (more than 8 row blocks), also row block w+8.
+//   The register footprint per wave stays that of one row block: the wave
+//   runs its two blocks one after the other.
 //
 //   Each hidden layer is Z = W_l H (all channels at once, N = 16*NCB columns)
 //   on FP32 MFMA 16x16x4.  The A operand (weights) streams from a
@@ -442,9 +445,100 @@ __host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB) {
 }
 
 // ---------------------------------------------------------------------------
+// Backward pieces of one row block, for workgroups whose waves own two row
+// blocks (the one-row-block path runs the same steps inline)
+// ---------------------------------------------------------------------------
+
+// hbar_H = W_{H+1}^T ybar for the rows of row block rb
+template <int D, int NCB>
+__device__ __forceinline__ void out_adjoint_rows(v4f (&acc)[NCB], const float* __restrict__ Wop, const float* yb,
+                                                 int Wp, int rb, int g, int j) {
+  constexpr int NCOL = 16 * NCB;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * rb + 4 * g + i;
+    float wo[D];
+#pragma unroll
+    for (int o = 0; o < D; ++o) wo[o] = ldg(Wop + o * Wp + r);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      float s = 0.f;
+#pragma unroll
+      for (int o = 0; o < D; ++o) s += wo[o] * yb[o * NCOL + 16 * cb + j];
+      acc[cb][i] = s;
+    }
+  }
+}
+
+// layer l, row block rb: zbar from hbar (acc, in place) and z_l (zs); db_l;
+// at l = 1 the input-layer gradient dW1
+template <int DIM, int NCB, int MODE, int ACT>
+__device__ __forceinline__ void adjoint_rows(v4f (&acc)[NCB], const v4f (&zs)[NCB], float* dbacc, float* acc1,
+                                             const float* xin, int Wp, int rb, int l, int g, int j) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int D = DIM + 1;
+  act_adjoint<DIM, NCB, MODE, ACT>(acc, zs);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float s = 0.f;
+#pragma unroll
+    for (int pb = 0; pb < M::NPB; ++pb) s += acc[pb][i];
+    s = sum16(s);
+    if (j == 0) dbacc[(l - 1) * Wp + 16 * rb + 4 * g + i] += s;
+  }
+  if (l != 1) return;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = 16 * rb + 4 * g + i;
+    float v[D];
+#pragma unroll
+    for (int q = 0; q < D; ++q) v[q] = 0.f;
+#pragma unroll
+    for (int pb = 0; pb < M::NPB; ++pb) {
+      const float* xp = xin + (16 * pb + j) * D;
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        v[q] += acc[pb][i] * xp[q];
+        if constexpr (MODE == M_PDE) v[q] += acc[(1 + q) * M::NPB + pb][i];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < D; ++q) {
+      const float s = sum16(v[q]);
+      if (j == 0) acc1[r * D + q] += s;
+    }
+  }
+}
+
+// dW_l += Zbar_l H_{l-1}^T for the rows of row block rb, into the layer's
+// block sw of the segment's slab; the old values are requested before each
+// chunk's GEMM so the read overlaps it
+template <int NCB>
+__device__ __forceinline__ void dw_rows(float* sw, bool first, const float* bufG, int S, const float* bufH, int S2,
+                                        int NW, int rb, int g, int j, uint32_t lo16) {
+  for (int nb0 = 0; nb0 < NW; nb0 += 4) {
+    const int nnb = (NW - nb0) < 4 ? (NW - nb0) : 4;
+    v4f old[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      old[t] = (t < nnb && !first) ? ldg4u(sw + (size_t)(rb * NW + nb0 + t) * 256, lo16) : zero4();
+    v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
+    switch (nnb) {
+      case 4: gemm_dw<NCB, 4>(bufG, S, bufH, S2, rb, g, j, nb0, dw); break;
+      case 3: gemm_dw<NCB, 3>(bufG, S, bufH, S2, rb, g, j, nb0, dw); break;
+      case 2: gemm_dw<NCB, 2>(bufG, S, bufH, S2, rb, g, j, nb0, dw); break;
+      default: gemm_dw<NCB, 1>(bufG, S, bufH, S2, rb, g, j, nb0, dw); break;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      if (t < nnb) stg4u(sw + (size_t)(rb * NW + nb0 + t) * 256, lo16, old[t] + dw[t]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused step kernel: persistent over this workgroup's item range.
 // ---------------------------------------------------------------------------
-template <int DIM, int PBP, int ACT>
+template <int DIM, int PBP, int ACT, int RPW>
 __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepArgs args) {
   constexpr int D = DIM + 1;
   constexpr int CF = 2 * DIM + 2;
@@ -455,7 +549,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   extern __shared__ float lds[];
 
   const Shape& sh = args.sh;
-  const int Wp = sh.Wp, NW = sh.NW, H = sh.H;
+  const int Wp = sh.Wp, NW = sh.NW, NWV = sh.NWV, H = sh.H;
   const int K4 = Wp / 16;
   const int tid = threadIdx.x, nthr = blockDim.x;
   // the wave index is uniform across a wave: keeping it in a scalar register
@@ -473,13 +567,20 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   float* red = lds + L.red;
   const int S = L.S, S2 = L.S2;
 
+  // row blocks of this wave: w, and w + NWV when there are more than NWV
+  const int nrb = (RPW == 1) ? 1 : (w + NWV < NW ? 2 : 1);
+  // stash: H pre-activation stacks per row block; a wave's second row block
+  // is NWV blocks further
   float* stash_w = args.stash + (size_t)blockIdx.x * args.stash_per_wg + (size_t)w * H * NCB * 256;
+  const size_t stash_rb = (size_t)NWV * H * NCB * 256;
   const uint32_t lo16 = (uint32_t)lane * 16u;   // this lane's byte offset in a 1 KiB wave fragment
   const float nu = args.nu;
 
-  // segment accumulators
+  // segment accumulators; dW_{H+1} entry tid + r*nthr is thread tid's
   float lacc[6];
-  float dwo = 0.f, dbo = 0.f;
+  float dwo[RPW], dbo = 0.f;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) dwo[r] = 0.f;
 
   // Item ranges: range blockIdx.x, or, with a counter, ranges taken in turn
   // until none is left (workgroups that share a compute unit do not progress
@@ -517,7 +618,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     if (item.flags & ITEM_FIRST) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) lacc[k] = 0.f;
-      dwo = 0.f;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r) dwo[r] = 0.f;
       dbo = 0.f;
       for (int k = tid; k < Wp * D; k += nthr) acc1[k] = 0.f;
       for (int k = tid; k < H * Wp; k += nthr) dbacc[k] = 0.f;
@@ -550,37 +652,76 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     // work overlaps the other waves' GEMMs.
     float* hin = bufH;
     float* hout = bufG;
-    if (pde) input_layer<DIM, NCB, M_PDE>(acc, W1p, bp, xin, w, g, j);
-    else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
+    if constexpr (RPW == 1) {
+      if (pde) input_layer<DIM, NCB, M_PDE>(acc, W1p, bp, xin, w, g, j);
+      else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + (0 * NCB + cb) * 256, lo16, acc[cb]);
-    if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
-    else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
-    store_fwd<NCB>(hin, S, acc, w, g, j);
-    __syncthreads();
-
-    // ---- forward: hidden layers 2..H
-    for (int l = 2; l <= H; ++l) {
-      const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
-      // The two waves sharing a SIMD run the same GEMM; the hardware favours
-      // the older one, which then idles at the next barrier while the younger
-      // finishes.  Raising the younger half's priority for the GEMM evens them.
-      if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-      gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
-      __builtin_amdgcn_s_setprio(0);
-      if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, g);
-      else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16, acc[cb]);
+      for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + (0 * NCB + cb) * 256, lo16, acc[cb]);
       if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
       else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
-      store_fwd<NCB>(hout, S, acc, w, g, j);
+      store_fwd<NCB>(hin, S, acc, w, g, j);
       __syncthreads();
-      float* t = hin;
-      hin = hout;
-      hout = t;
+
+      // ---- forward: hidden layers 2..H
+      for (int l = 2; l <= H; ++l) {
+        const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+        // The two waves sharing a SIMD run the same GEMM; the hardware favours
+        // the older one, which then idles at the next barrier while the younger
+        // finishes.  Raising the younger half's priority for the GEMM evens them.
+        if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
+        gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
+        __builtin_amdgcn_s_setprio(0);
+        if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, g);
+        else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16, acc[cb]);
+        if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
+        else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
+        store_fwd<NCB>(hout, S, acc, w, g, j);
+        __syncthreads();
+        float* t = hin;
+        hin = hout;
+        hout = t;
+      }
+    } else {
+      // two row blocks per wave: the same steps per row block
+      for (int r = 0; r < nrb; ++r) {
+        const int rb = w + r * NWV;
+        float* st = stash_w + r * stash_rb;
+        if (pde) input_layer<DIM, NCB, M_PDE>(acc, W1p, bp, xin, rb, g, j);
+        else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, rb, g, j);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) stg4u(st + (0 * NCB + cb) * 256, lo16, acc[cb]);
+        if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
+        else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
+        store_fwd<NCB>(hin, S, acc, rb, g, j);
+      }
+      __syncthreads();
+      for (int l = 2; l <= H; ++l) {
+        for (int r = 0; r < nrb; ++r) {
+          const int rb = w + r * NWV;
+          float* st = stash_w + r * stash_rb;
+          const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)rb * 16 * Wp;
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+          if (w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
+          gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
+          __builtin_amdgcn_s_setprio(0);
+          if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, rb, g);
+          else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, rb, g);
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) stg4u(st + ((l - 1) * NCB + cb) * 256, lo16, acc[cb]);
+          if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
+          else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
+          store_fwd<NCB>(hout, S, acc, rb, g, j);
+        }
+        __syncthreads();
+        float* t = hin;
+        hin = hout;
+        hout = t;
+      }
     }
 
     // ---- output layer (h_H is in hin)
@@ -679,133 +820,221 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     }
     __syncthreads();
 
-    // ---- output layer adjoint (z_H is fetched from the stash meanwhile)
-    v4f zs[NCB];
+    if constexpr (RPW == 1) {
+      // ---- output layer adjoint (z_H is fetched from the stash meanwhile)
+      v4f zs[NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
-      zs[cb] = ldg4u(stash_w + ((H - 1) * NCB + cb) * 256, lo16);
-    {
-      const int npb = pde ? MP::NPB : MV::NPB;
-      if (tid < D * Wp) {
-        const int o = tid / Wp, n = tid - o * Wp;
-        float s = 0.f;
-        for (int col = 0; col < NCOL; ++col) s += yb[o * NCOL + col] * hin[col * S + n];
-        dwo += s;
-      }
-      if (tid < D) {
-        float s = 0.f;
-        for (int col = 0; col < 16 * npb; ++col) s += yb[tid * NCOL + col];
-        dbo += s;
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int r = 16 * w + 4 * g + i;
-        float wo[D];
-#pragma unroll
-        for (int o = 0; o < D; ++o) wo[o] = ldg(Wop + o * Wp + r);
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) {
-          float s = 0.f;
-#pragma unroll
-          for (int o = 0; o < D; ++o) s += wo[o] * yb[o * NCOL + 16 * cb + j];
-          acc[cb][i] = s;
-        }
-      }
-    }
-
-    // ---- hidden and input layer adjoints
-    for (int l = H; l >= 1; --l) {
-      if (pde) act_adjoint<DIM, NCB, M_PDE, ACT>(acc, zs);
-      else act_adjoint<DIM, NCB, M_VALUE, ACT>(acc, zs);
-      // db_l: value-channel columns
+      for (int cb = 0; cb < NCB; ++cb)
+        zs[cb] = ldg4u(stash_w + ((H - 1) * NCB + cb) * 256, lo16);
       {
         const int npb = pde ? MP::NPB : MV::NPB;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        if (tid < D * Wp) {
+          const int o = tid / Wp, n = tid - o * Wp;
           float s = 0.f;
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb)
-            if (cb < npb) s += acc[cb][i];
-          s = sum16(s);
-          if (j == 0) dbacc[(l - 1) * Wp + 16 * w + 4 * g + i] += s;
+          for (int col = 0; col < NCOL; ++col) s += yb[o * NCOL + col] * hin[col * S + n];
+          dwo[0] += s;
         }
-      }
-      if (l == 1) {
-        // input layer: dW1[r][q] += sum_pts zbar0 xi_q + zbar_q (first-derivative channel q)
+        if (tid < D) {
+          float s = 0.f;
+          for (int col = 0; col < 16 * npb; ++col) s += yb[tid * NCOL + col];
+          dbo += s;
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int r = 16 * w + 4 * g + i;
-          float v[D];
+          float wo[D];
 #pragma unroll
-          for (int q = 0; q < D; ++q) v[q] = 0.f;
-          if (pde) {
+          for (int o = 0; o < D; ++o) wo[o] = ldg(Wop + o * Wp + r);
 #pragma unroll
-            for (int pb = 0; pb < MP::NPB; ++pb) {
-              const float* xp = xin + (16 * pb + j) * D;
+          for (int cb = 0; cb < NCB; ++cb) {
+            float s = 0.f;
 #pragma unroll
-              for (int q = 0; q < D; ++q)
-                v[q] += acc[pb][i] * xp[q] + acc[(1 + q) * MP::NPB + pb][i];
-            }
-          } else {
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) {
-              const float* xp = xin + (16 * cb + j) * D;
-#pragma unroll
-              for (int q = 0; q < D; ++q) v[q] += acc[cb][i] * xp[q];
-            }
-          }
-#pragma unroll
-          for (int q = 0; q < D; ++q) {
-            const float s = sum16(v[q]);
-            if (j == 0) acc1[r * D + q] += s;
+            for (int o = 0; o < D; ++o) s += wo[o] * yb[o * NCOL + 16 * cb + j];
+            acc[cb][i] = s;
           }
         }
-        break;
       }
-      // z_{l-1} from the stash (kept for the next adjoint); then wait until
-      // every wave has finished reading the LDS stacks before overwriting them
+
+      // ---- hidden and input layer adjoints
+      for (int l = H; l >= 1; --l) {
+        if (pde) act_adjoint<DIM, NCB, M_PDE, ACT>(acc, zs);
+        else act_adjoint<DIM, NCB, M_VALUE, ACT>(acc, zs);
+        // db_l: value-channel columns
+        {
+          const int npb = pde ? MP::NPB : MV::NPB;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float s = 0.f;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              if (cb < npb) s += acc[cb][i];
+            s = sum16(s);
+            if (j == 0) dbacc[(l - 1) * Wp + 16 * w + 4 * g + i] += s;
+          }
+        }
+        if (l == 1) {
+          // input layer: dW1[r][q] += sum_pts zbar0 xi_q + zbar_q (first-derivative channel q)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = 16 * w + 4 * g + i;
+            float v[D];
+#pragma unroll
+            for (int q = 0; q < D; ++q) v[q] = 0.f;
+            if (pde) {
+#pragma unroll
+              for (int pb = 0; pb < MP::NPB; ++pb) {
+                const float* xp = xin + (16 * pb + j) * D;
+#pragma unroll
+                for (int q = 0; q < D; ++q)
+                  v[q] += acc[pb][i] * xp[q] + acc[(1 + q) * MP::NPB + pb][i];
+              }
+            } else {
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) {
+                const float* xp = xin + (16 * cb + j) * D;
+#pragma unroll
+                for (int q = 0; q < D; ++q) v[q] += acc[cb][i] * xp[q];
+              }
+            }
+#pragma unroll
+            for (int q = 0; q < D; ++q) {
+              const float s = sum16(v[q]);
+              if (j == 0) acc1[r * D + q] += s;
+            }
+          }
+          break;
+        }
+        // z_{l-1} from the stash (kept for the next adjoint); then wait until
+        // every wave has finished reading the LDS stacks before overwriting them
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          zs[cb] = ldg4u(stash_w + ((l - 2) * NCB + cb) * 256, lo16);
+        __syncthreads();
+        store_fwd<NCB>(bufG, S, acc, w, g, j);
+        // recompute h_{l-1} from z_{l-1}
+        if (pde) act_store_bwd<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w, g, j);
+        else act_store_bwd<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w, g, j);
+        __syncthreads();
+        // dW_l += Zbar_l H_{l-1}^T into this segment's slab; the slab's current
+        // values are requested before each chunk's GEMM so the read overlaps it
+        {
+          float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
+          const bool first = item.flags & ITEM_FIRST;
+          if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);   // as in the forward GEMM
+          for (int nb0 = 0; nb0 < NW; nb0 += 4) {
+            const int nnb = (NW - nb0) < 4 ? (NW - nb0) : 4;
+            v4f old[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              old[t] = (t < nnb && !first) ? ldg4u(sw + (size_t)(w * NW + nb0 + t) * 256, lo16) : zero4();
+            v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
+            switch (nnb) {
+              case 4: gemm_dw<NCB, 4>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
+              case 3: gemm_dw<NCB, 3>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
+              case 2: gemm_dw<NCB, 2>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
+              default: gemm_dw<NCB, 1>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (t < nnb) stg4u(sw + (size_t)(w * NW + nb0 + t) * 256, lo16, old[t] + dw[t]);
+          }
+        }
+        __builtin_amdgcn_s_setprio(0);
+        // Hbar_{l-1} = W_l^T Zbar_l
+        {
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+          const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
+          if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
+          gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc);
+          __builtin_amdgcn_s_setprio(0);
+        }
+      }
+    } else {
+      // ---- two row blocks per wave (more than 8 row blocks): the same steps
+      // per row block.  Only one block's zbar fits in registers across a
+      // barrier, so the first block's waits in its own stash slot (z_l of
+      // that block is dead once its adjoint has run).
+      v4f zs[NCB];
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
-        zs[cb] = ldg4u(stash_w + ((l - 2) * NCB + cb) * 256, lo16);
-      __syncthreads();
-      store_fwd<NCB>(bufG, S, acc, w, g, j);
-      // recompute h_{l-1} from z_{l-1}
-      if (pde) act_store_bwd<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w, g, j);
-      else act_store_bwd<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w, g, j);
-      __syncthreads();
-      // dW_l += Zbar_l H_{l-1}^T into this segment's slab; the slab's current
-      // values are requested before each chunk's GEMM so the read overlaps it
+        zs[cb] = ldg4u(stash_w + ((H - 1) * NCB + cb) * 256, lo16);
       {
-        float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
-        const bool first = item.flags & ITEM_FIRST;
-        if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);   // as in the forward GEMM
-        for (int nb0 = 0; nb0 < NW; nb0 += 4) {
-          const int nnb = (NW - nb0) < 4 ? (NW - nb0) : 4;
-          v4f old[4];
+        const int npb = pde ? MP::NPB : MV::NPB;
 #pragma unroll
-          for (int t = 0; t < 4; ++t)
-            old[t] = (t < nnb && !first) ? ldg4u(sw + (size_t)(w * NW + nb0 + t) * 256, lo16) : zero4();
-          v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
-          switch (nnb) {
-            case 4: gemm_dw<NCB, 4>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
-            case 3: gemm_dw<NCB, 3>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
-            case 2: gemm_dw<NCB, 2>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
-            default: gemm_dw<NCB, 1>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
+        for (int r = 0; r < RPW; ++r) {
+          const int idx = tid + r * nthr;
+          if (idx < D * Wp) {
+            const int o = idx / Wp, n = idx - o * Wp;
+            float s = 0.f;
+            for (int col = 0; col < NCOL; ++col) s += yb[o * NCOL + col] * hin[col * S + n];
+            dwo[r] += s;
           }
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (t < nnb) stg4u(sw + (size_t)(w * NW + nb0 + t) * 256, lo16, old[t] + dw[t]);
+        }
+        if (tid < D) {
+          float s = 0.f;
+          for (int col = 0; col < 16 * npb; ++col) s += yb[tid * NCOL + col];
+          dbo += s;
         }
       }
-      __builtin_amdgcn_s_setprio(0);
-      // Hbar_{l-1} = W_l^T Zbar_l
-      {
+      const bool raise = w >= (NWV >> 1);   // wave priority for the GEMMs, as in the forward
+      for (int r = 0; r < nrb; ++r) {
+        const int rb = w + r * NWV;
+        float* st = stash_w + r * stash_rb;
+        if (r > 0) {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
-        const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
-        if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-        gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc);
+          for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(st + ((H - 1) * NCB + cb) * 256, lo16);
+        }
+        out_adjoint_rows<D, NCB>(acc, Wop, yb, Wp, rb, g, j);
+        if (pde) adjoint_rows<DIM, NCB, M_PDE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, H, g, j);
+        else adjoint_rows<DIM, NCB, M_VALUE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, H, g, j);
+        if (H > 1 && r + 1 < nrb) {
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) stg4u(st + ((H - 1) * NCB + cb) * 256, lo16, acc[cb]);
+        }
+      }
+      for (int l = H; l >= 2; --l) {
+        __syncthreads();
+        // Zbar_l into LDS: the last block's from registers, the first's from the stash
+        store_fwd<NCB>(bufG, S, acc, w + (nrb - 1) * NWV, g, j);
+        if (nrb == 2) {
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[cb] = ldg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16);
+          store_fwd<NCB>(bufG, S, acc, w, g, j);
+        }
+        // h_{l-1} recomputed from z_{l-1}
+        for (int r = 0; r < nrb; ++r) {
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            zs[cb] = ldg4u(stash_w + r * stash_rb + ((l - 2) * NCB + cb) * 256, lo16);
+          if (pde) act_store_bwd<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w + r * NWV, g, j);
+          else act_store_bwd<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w + r * NWV, g, j);
+        }
+        __syncthreads();
+        float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
+        if (raise) __builtin_amdgcn_s_setprio(2);
+        for (int r = 0; r < nrb; ++r)
+          dw_rows<NCB>(sw, item.flags & ITEM_FIRST, bufG, S, bufH, S2, NW, w + r * NWV, g, j, lo16);
         __builtin_amdgcn_s_setprio(0);
+        // Hbar_{l-1} = W_l^T Zbar_l, then the adjoint of layer l-1, per block
+        for (int r = 0; r < nrb; ++r) {
+          const int rb = w + r * NWV;
+          float* st = stash_w + r * stash_rb;
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(st + ((l - 2) * NCB + cb) * 256, lo16);
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+          const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)rb * 16 * Wp;
+          if (raise) __builtin_amdgcn_s_setprio(2);
+          gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc);
+          __builtin_amdgcn_s_setprio(0);
+          if (pde) adjoint_rows<DIM, NCB, M_PDE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
+          else adjoint_rows<DIM, NCB, M_VALUE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
+          if (l > 2 && r + 1 < nrb) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) stg4u(st + ((l - 2) * NCB + cb) * 256, lo16, acc[cb]);
+          }
+        }
       }
     }
 
@@ -815,7 +1044,9 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       float* slab = args.slabs + (size_t)item.slab * sh.slab_floats;
       for (int k = tid; k < Wp * D; k += nthr) slab[sh.s_w1 + k] = acc1[k];
       for (int k = tid; k < H * Wp; k += nthr) slab[sh.s_b + k] = dbacc[k];
-      if (tid < D * Wp) slab[sh.s_wo + tid] = dwo;
+#pragma unroll
+      for (int r = 0; r < RPW; ++r)
+        if (tid + r * nthr < D * Wp) slab[sh.s_wo + tid + r * nthr] = dwo[r];
       if (tid < 4) slab[sh.s_bo + tid] = (tid < D) ? dbo : 0.f;
       // loss partials: wave sums, then across waves
 #pragma unroll
@@ -828,7 +1059,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       if (tid < 8) {
         float v = 0.f;
         if (tid < 6)
-          for (int q = 0; q < NW; ++q) v += red[q * 8 + tid];
+          for (int q = 0; q < NWV; ++q) v += red[q * 8 + tid];
         slab[sh.s_loss + tid] = v;
       }
       __syncthreads();
@@ -1097,34 +1328,51 @@ __host__ __device__ inline QueryLds query_lds(int D, int Wp, int NCB) {
   return L;
 }
 
-// forward of one staged tile (points in xin) through all layers; output in ys
-template <int DIM, int NCB, int MODE, int ACT>
+// forward of one staged tile (points in xin) through all layers; output in ys.
+// Wave w computes row block w and, with RPW = 2, row block w + NWV; one LDS
+// stack, so every block's accumulators wait in registers until all waves have
+// read the stack.
+template <int DIM, int NCB, int MODE, int ACT, int RPW>
 __device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, float* bufH, float* ys,
                                              const float* xin, int S, int tid, int nthr, int w, int g,
                                              int j, int lane) {
   using M = ModeCfg<DIM, NCB, MODE>;
-  const int Wp = sh.Wp, H = sh.H, K4 = Wp / 16;
-  v4f acc[NCB];
-  input_layer<DIM, NCB, MODE>(acc, fr + sh.f_w1, fr + sh.f_b, xin, w, g, j);
-  act_forward<DIM, NCB, MODE, ACT>(acc);
-  store_fwd<NCB>(bufH, S, acc, w, g, j);
+  const int Wp = sh.Wp, H = sh.H, K4 = Wp / 16, NWV = sh.NWV;
+  const int nrb = (RPW == 1) ? 1 : (w + NWV < sh.NW ? 2 : 1);
+  v4f acc[RPW][NCB];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    if (r >= nrb) break;
+    input_layer<DIM, NCB, MODE>(acc[r], fr + sh.f_w1, fr + sh.f_b, xin, w + r * NWV, g, j);
+    act_forward<DIM, NCB, MODE, ACT>(acc[r]);
+    store_fwd<NCB>(bufH, S, acc[r], w + r * NWV, g, j);
+  }
   __syncthreads();
   for (int l = 2; l <= H; ++l) {
-    const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
-    gemm_rows<NCB>(Wf, bufH, S, K4, g, j, lane, acc);
-    add_bias<NCB, M::NPB>(acc, fr + sh.f_b + (l - 1) * Wp, w, g);
+    for (int r = 0; r < RPW; ++r) {
+      if (r >= nrb) break;
+      const int rb = w + r * NWV;
+      const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)rb * 16 * Wp;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = zero4();
+      gemm_rows<NCB>(Wf, bufH, S, K4, g, j, lane, acc[r]);
+      add_bias<NCB, M::NPB>(acc[r], fr + sh.f_b + (l - 1) * Wp, rb, g);
+    }
     __syncthreads();
-    act_forward<DIM, NCB, MODE, ACT>(acc);
-    store_fwd<NCB>(bufH, S, acc, w, g, j);
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (r >= nrb) break;
+      act_forward<DIM, NCB, MODE, ACT>(acc[r]);
+      store_fwd<NCB>(bufH, S, acc[r], w + r * NWV, g, j);
+    }
     __syncthreads();
   }
   output_layer<DIM, NCB, MODE>(bufH, S, Wp, fr + sh.f_wo, fr + sh.f_bo, ys, tid, nthr);
   __syncthreads();
 }
 
-template <int DIM, int MODE, int ACT>
+template <int DIM, int MODE, int ACT, int RPW>
 __global__ __launch_bounds__(512) void query_kernel(const QueryArgs a) {
   constexpr int D = DIM + 1, CF = 2 * DIM + 2, NCB = CF;
   using M = ModeCfg<DIM, NCB, MODE>;
@@ -1179,7 +1427,7 @@ __global__ __launch_bounds__(512) void query_kernel(const QueryArgs a) {
       xin[k] = v;
     }
     __syncthreads();
-    forward_tile<DIM, NCB, MODE, ACT>(sh, a.subs[sub].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
+    forward_tile<DIM, NCB, MODE, ACT, RPW>(sh, a.subs[sub].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
     for (int k = tid; k < NPTS; k += nthr) {
       if (pidx[k] < 0) continue;
       const int64_t q = pidx[k];
@@ -1213,7 +1461,7 @@ __global__ __launch_bounds__(512) void query_kernel(const QueryArgs a) {
 // ---------------------------------------------------------------------------
 // exchange: neighbour values at ghost points, anchor-normalised pressure
 // ---------------------------------------------------------------------------
-template <int DIM, int ACT>
+template <int DIM, int ACT, int RPW>
 __global__ __launch_bounds__(512) void exchange_kernel(const ExchangeArgs a) {
   constexpr int D = DIM + 1, CF = 2 * DIM + 2, NCB = CF, NCOL = 16 * NCB;
   extern __shared__ float lds[];
@@ -1243,7 +1491,7 @@ __global__ __launch_bounds__(512) void exchange_kernel(const ExchangeArgs a) {
       xin[k] = v;
     }
     __syncthreads();
-    forward_tile<DIM, NCB, M_VALUE, ACT>(sh, a.subs[it.b].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
+    forward_tile<DIM, NCB, M_VALUE, ACT, RPW>(sh, a.subs[it.b].frag, bufH, ys, xin, L.S, tid, nthr, w, g, j, lane);
     float* tg = a.targets[it.a];
     for (int k = tid; k < it.count; k += nthr) {
       for (int o = 0; o < D; ++o) {
@@ -1411,13 +1659,24 @@ int query_lds_floats(const Shape& sh) {
   return query_lds(sh.D, sh.Wp, 2 * sh.dim + 2).total;
 }
 
-template <int DIM, int PBP>
-static const void* step_ptr_act(int act) {
-  return act == ACT_SIN ? (const void*)step_kernel<DIM, PBP, ACT_SIN> : (const void*)step_kernel<DIM, PBP, ACT_TANH>;
+// Kernel instances: dimension, tile (16 or 32 collocation points), activation
+// and row blocks per wave (2 above 8 row blocks; 16-point tiles only).
+static const void* step_ptr(int dim, int tile_points, int act, int rpw) {
+  if (rpw == 2) {
+    if (dim == 2) return act == ACT_SIN ? (const void*)step_kernel<2, 1, ACT_SIN, 2> : (const void*)step_kernel<2, 1, ACT_TANH, 2>;
+    return act == ACT_SIN ? (const void*)step_kernel<3, 1, ACT_SIN, 2> : (const void*)step_kernel<3, 1, ACT_TANH, 2>;
+  }
+  if (dim == 2) {
+    if (tile_points == 32) return act == ACT_SIN ? (const void*)step_kernel<2, 2, ACT_SIN, 1> : (const void*)step_kernel<2, 2, ACT_TANH, 1>;
+    return act == ACT_SIN ? (const void*)step_kernel<2, 1, ACT_SIN, 1> : (const void*)step_kernel<2, 1, ACT_TANH, 1>;
+  }
+  if (tile_points == 32) return act == ACT_SIN ? (const void*)step_kernel<3, 2, ACT_SIN, 1> : (const void*)step_kernel<3, 2, ACT_TANH, 1>;
+  return act == ACT_SIN ? (const void*)step_kernel<3, 1, ACT_SIN, 1> : (const void*)step_kernel<3, 1, ACT_TANH, 1>;
 }
-const void* step_kernel_ptr(int dim, int tile_points, int act) {
-  if (dim == 2) return tile_points == 32 ? step_ptr_act<2, 2>(act) : step_ptr_act<2, 1>(act);
-  return tile_points == 32 ? step_ptr_act<3, 2>(act) : step_ptr_act<3, 1>(act);
+static int rows_per_wave(const Shape& sh) { return sh.NW > sh.NWV ? 2 : 1; }
+const void* step_kernel_ptr(const Shape& sh, int tile_points) {
+  if (rows_per_wave(sh) == 2 && tile_points != 16) return nullptr;
+  return step_ptr(sh.dim, tile_points, sh.act, rows_per_wave(sh));
 }
 const void* prep_kernel_ptr() { return (const void*)prep_kernel; }
 const void* slab_sum_kernel_ptr() { return (const void*)slab_sum_kernel; }
@@ -1447,9 +1706,11 @@ hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
 
 hipError_t launch_step(const StepArgs& a, int tile_points, int n_wg, hipStream_t s) {
   const size_t lds = (size_t)a.lds_floats * sizeof(float);
-  const dim3 block(a.sh.NW * 64);
+  const void* k = step_kernel_ptr(a.sh, tile_points);
+  if (!k) return hipErrorInvalidValue;
+  const dim3 block(a.sh.NWV * 64);
   void* args[] = {const_cast<StepArgs*>(&a)};
-  return hipLaunchKernel(step_kernel_ptr(a.sh.dim, tile_points, a.sh.act), dim3(n_wg), block, args, lds, s);
+  return hipLaunchKernel(k, dim3(n_wg), block, args, lds, s);
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
@@ -1473,55 +1734,66 @@ hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int DIM, int MODE>
+template <int DIM, int MODE, int RPW>
 static const void* query_ptr_act(int act) {
-  return act == ACT_SIN ? (const void*)query_kernel<DIM, MODE, ACT_SIN> : (const void*)query_kernel<DIM, MODE, ACT_TANH>;
+  return act == ACT_SIN ? (const void*)query_kernel<DIM, MODE, ACT_SIN, RPW> : (const void*)query_kernel<DIM, MODE, ACT_TANH, RPW>;
 }
-
-const void* query_kernel_ptr(int dim, int what, int act) {
+template <int DIM, int RPW>
+static const void* query_ptr_mode(int mode, int act) {
+  return mode == M_VALUE ? query_ptr_act<DIM, M_VALUE, RPW>(act)
+                         : (mode == M_GRAD ? query_ptr_act<DIM, M_GRAD, RPW>(act) : query_ptr_act<DIM, M_PDE, RPW>(act));
+}
+static const void* query_ptr(int dim, int mode, int act, int rpw) {
+  if (dim == 2) return rpw == 2 ? query_ptr_mode<2, 2>(mode, act) : query_ptr_mode<2, 1>(mode, act);
+  return rpw == 2 ? query_ptr_mode<3, 2>(mode, act) : query_ptr_mode<3, 1>(mode, act);
+}
+const void* query_kernel_ptr(const Shape& sh, int what) {
   const int mode = (what == Q_VALUE) ? M_VALUE : (what == Q_UVPW ? M_GRAD : M_PDE);
-  if (dim == 2)
-    return mode == M_VALUE ? query_ptr_act<2, M_VALUE>(act) : (mode == M_GRAD ? query_ptr_act<2, M_GRAD>(act) : query_ptr_act<2, M_PDE>(act));
-  return mode == M_VALUE ? query_ptr_act<3, M_VALUE>(act) : (mode == M_GRAD ? query_ptr_act<3, M_GRAD>(act) : query_ptr_act<3, M_PDE>(act));
+  return query_ptr(sh.dim, mode, sh.act, rows_per_wave(sh));
 }
 
-const void* exchange_kernel_ptr(int dim, int act) {
-  if (dim == 2) return act == ACT_SIN ? (const void*)exchange_kernel<2, ACT_SIN> : (const void*)exchange_kernel<2, ACT_TANH>;
-  return act == ACT_SIN ? (const void*)exchange_kernel<3, ACT_SIN> : (const void*)exchange_kernel<3, ACT_TANH>;
+static const void* exchange_ptr(int dim, int act, int rpw) {
+  if (rpw == 2) {
+    if (dim == 2) return act == ACT_SIN ? (const void*)exchange_kernel<2, ACT_SIN, 2> : (const void*)exchange_kernel<2, ACT_TANH, 2>;
+    return act == ACT_SIN ? (const void*)exchange_kernel<3, ACT_SIN, 2> : (const void*)exchange_kernel<3, ACT_TANH, 2>;
+  }
+  if (dim == 2) return act == ACT_SIN ? (const void*)exchange_kernel<2, ACT_SIN, 1> : (const void*)exchange_kernel<2, ACT_TANH, 1>;
+  return act == ACT_SIN ? (const void*)exchange_kernel<3, ACT_SIN, 1> : (const void*)exchange_kernel<3, ACT_TANH, 1>;
 }
+const void* exchange_kernel_ptr(const Shape& sh) { return exchange_ptr(sh.dim, sh.act, rows_per_wave(sh)); }
 
 hipError_t launch_query(const QueryArgs& a, int n_wg, hipStream_t s) {
   if (n_wg >= 16) n_wg &= ~7;   // a multiple of the XCD count (see query_kernel)
   const size_t lds = (size_t)a.lds_floats * sizeof(float);
-  const dim3 block(a.sh.NW * 64);
+  const dim3 block(a.sh.NWV * 64);
   void* args[] = {const_cast<QueryArgs*>(&a)};
-  return hipLaunchKernel(query_kernel_ptr(a.sh.dim, a.what, a.sh.act), dim3(n_wg), block, args, lds, s);
+  return hipLaunchKernel(query_kernel_ptr(a.sh, a.what), dim3(n_wg), block, args, lds, s);
 }
 
 hipError_t launch_exchange(const ExchangeArgs& a, int n_wg, hipStream_t s) {
   const size_t lds = (size_t)a.lds_floats * sizeof(float);
-  const dim3 block(a.sh.NW * 64);
+  const dim3 block(a.sh.NWV * 64);
   void* args[] = {const_cast<ExchangeArgs*>(&a)};
-  return hipLaunchKernel(exchange_kernel_ptr(a.sh.dim, a.sh.act), dim3(n_wg), block, args, lds, s);
+  return hipLaunchKernel(exchange_kernel_ptr(a.sh), dim3(n_wg), block, args, lds, s);
 }
 
 // LDS above 64 KiB must be allowed per kernel before launch.
 hipError_t set_lds_limits(int bytes) {
   hipError_t e = hipSuccess;
-  const void* ks[] = {
-      step_kernel_ptr(2, 16, ACT_TANH), step_kernel_ptr(2, 32, ACT_TANH), step_kernel_ptr(3, 16, ACT_TANH),
-      step_kernel_ptr(3, 32, ACT_TANH), step_kernel_ptr(2, 16, ACT_SIN), step_kernel_ptr(2, 32, ACT_SIN),
-      step_kernel_ptr(3, 16, ACT_SIN), step_kernel_ptr(3, 32, ACT_SIN),
-      query_ptr_act<2, M_VALUE>(ACT_TANH), query_ptr_act<2, M_GRAD>(ACT_TANH), query_ptr_act<2, M_PDE>(ACT_TANH),
-      query_ptr_act<3, M_VALUE>(ACT_TANH), query_ptr_act<3, M_GRAD>(ACT_TANH), query_ptr_act<3, M_PDE>(ACT_TANH),
-      query_ptr_act<2, M_VALUE>(ACT_SIN), query_ptr_act<2, M_GRAD>(ACT_SIN), query_ptr_act<2, M_PDE>(ACT_SIN),
-      query_ptr_act<3, M_VALUE>(ACT_SIN), query_ptr_act<3, M_GRAD>(ACT_SIN), query_ptr_act<3, M_PDE>(ACT_SIN),
-      (const void*)exchange_kernel<2, ACT_TANH>, (const void*)exchange_kernel<3, ACT_TANH>,
-      (const void*)exchange_kernel<2, ACT_SIN>, (const void*)exchange_kernel<3, ACT_SIN>};
-  for (const void* k : ks) {
-    hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  auto allow = [&](const void* k) {
+    const hipError_t r = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (r != hipSuccess) e = r;
-  }
+  };
+  for (int dim = 2; dim <= 3; ++dim)
+    for (int act = ACT_TANH; act <= ACT_SIN; ++act) {
+      allow(step_ptr(dim, 16, act, 1));
+      allow(step_ptr(dim, 32, act, 1));
+      allow(step_ptr(dim, 16, act, 2));
+      for (int rpw = 1; rpw <= 2; ++rpw) {
+        for (int mode : {M_PDE, M_VALUE, M_GRAD}) allow(query_ptr(dim, mode, act, rpw));
+        allow(exchange_ptr(dim, act, rpw));
+      }
+    }
   return e;
 }
 

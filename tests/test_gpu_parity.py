@@ -229,8 +229,7 @@ def test_empty_sets_and_single_points(pkg, orc):
 def test_invalid_arguments_rejected(pkg):
     pb = wl.tiny(dim=2, width=5, depth=2)
     with pytest.raises(pkg.PinnError) as e:
-        pb.width = 129
-        ctx_of(pkg, wl.tiny(dim=2, width=129, depth=1))
+        ctx_of(pkg, wl.tiny(dim=2, width=257, depth=1))
     assert "UNSUPPORTED" in str(e.value)
     ctx = ctx_of(pkg, wl.tiny(dim=2, width=5, depth=2), graph=False)
     with pytest.raises(pkg.PinnError):

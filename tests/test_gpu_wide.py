@@ -1,0 +1,114 @@
+"""Networks wider than 128 neurons: each wave of the step, query and exchange
+kernels then owns two 16-neuron row blocks (w and w + 8).  Cases span a wave
+mix of one and two blocks (W = 150: waves 0-1 hold two; W = 144 in 3D: wave 0),
+all waves with two (W = 192), padding (W = 129 -> 144), both activations, the
+paper's 2D-cylinder network width (6 x 150, sine; section 3.2, appendix B),
+several tiles per workgroup, and the limits of the LDS plan."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from parity import TOL_GRAD, TOL_LOSS, TOL_RESIDUAL, assert_close, channel_tolerances, oracle_loss_grad
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2602_15883_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture
+def act_oracle(orc):
+    yield orc
+    orc.set_activation("tanh")
+
+
+# dim, width, depth, activation, collocation points
+WIDE = [(2, 150, 6, "sin", 87),      # the paper's 2D-cylinder network shape
+        (2, 150, 2, "tanh", 8201),   # > 1 tile per workgroup: slab read-modify-write
+        (2, 192, 2, "tanh", 87),     # every wave holds two row blocks
+        (3, 144, 2, "tanh", 300),
+        (3, 129, 3, "sin", 50)]      # padded to 144
+
+
+@pytest.mark.parametrize("dim,W,H,act,npde", WIDE)
+def test_wide_loss_grad_channels(pkg, act_oracle, dim, W, H, act, npde):
+    orc = act_oracle
+    orc.set_activation(act)
+    pb = wl.tiny(dim=dim, width=W, depth=H, n_pde=npde, n_obs=150, n_gh=30, n_anc=2, seed=W + H)
+    pb.activation = act
+    print(f"wide step dim={dim} W={W} H={H} act={act} n_pde={npde}", flush=True)
+    ctx = pkg.context_from_problem(pb, device="cuda", graph=True)
+    try:
+        assert ctx.launch_info()["threads"] == 512
+        loss, g = ctx.step(1, update=False, want_grad=True)
+        torch.cuda.synchronize()
+        Lr, gr = oracle_loss_grad(orc, pb)
+        assert_close(loss.cpu().numpy()[0].astype(np.float64), Lr, TOL_LOSS, "loss")
+        assert_close(g.cpu().numpy()[0].astype(np.float64), gr, TOL_GRAD, "grad")
+        x = pb.subs[0].pde_x[:200]
+        xt = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        ch = ctx.query(xt, sub=0, what="channels").cpu().numpy().reshape(len(x), 2 * dim + 2, dim + 1)
+        ref = orc.channels(dim, W, H, pb.subs[0].theta, x)
+        for c, tol in enumerate(channel_tolerances(dim)):
+            assert_close(ch[:, c], ref[:, c], tol, f"channel {c}")
+        r = ctx.query(xt, sub=0, what="residual").cpu().numpy()
+        assert_close(r, orc.residuals(dim, pb.nu, ref), TOL_RESIDUAL, "residuals")
+        v = ctx.query(xt, sub=0, what="value").cpu().numpy()
+        assert_close(v, ref[:, 0], 1e-5, "values")
+    finally:
+        ctx.close()
+
+
+def test_wide_routed_query_and_exchange(pkg, orc):
+    W, H = 150, 2
+    boxes, thetas = wl.serving_nets(seed=5, width=W, depth=H)
+    subs = [wl._sub(2, boxes[s][0], boxes[s][1], thetas[s]) for s in range(len(thetas))]
+    pb = wl.Problem("serve_wide", 2, W, H, 0.01, np.ones(6), 1e-3, subs)
+    print("wide routed query", flush=True)
+    ctx = pkg.context_from_problem(pb, device="cuda", graph=False)
+    try:
+        x = wl.query_points(np.random.default_rng(2), 2500)
+        out = ctx.query(torch.from_numpy(x).cuda(), sub=-1, what="uvpw").cpu().numpy()
+        ref = orc.query2d(W, H, thetas, boxes, x)
+        ok = ~np.isnan(ref[:, 0])
+        assert_close(out[ok, :3], ref[ok, :3], 1e-5, "query uvp")
+        assert_close(out[ok, 3], ref[ok, 3], 1e-4, "query vorticity")
+    finally:
+        ctx.close()
+
+    pb = wl.config3(0, width=W, depth=H, pde_range=(100, 200), n_obs=10, n_gh_face=50)
+    print("wide exchange", flush=True)
+    ctx = pkg.context_from_problem(pb, device="cuda", graph=False)
+    try:
+        faces, targets = [], []
+        for a, s in enumerate(pb.subs):
+            for (b, kind, first, count) in s.faces:
+                faces.append((a, b, first, count))
+            targets.append(torch.zeros(s.gh_x.shape[0], 3, dtype=torch.float32, device="cuda"))
+        ctx.exchange(faces, pb.x_anc, targets)
+        torch.cuda.synchronize()
+        for (a, b, first, count) in faces:
+            xg = pb.subs[a].gh_x[first:first + count]
+            ref = orc.exchange(2, W, H, pb.subs[b].theta, pb.subs[b].is_master, pb.x_anc, xg)
+            got = targets[a][first:first + count].cpu().numpy()
+            assert_close(got[:, :2], ref[:, :2], 1e-5, f"exchange u {a}<-{b}")
+            assert_close(got[:, 2], ref[:, 2], 1e-4, f"exchange p {a}<-{b}")
+    finally:
+        ctx.close()
+
+
+def test_wide_limits(pkg):
+    """Tiles that do not fit in LDS (the paper's 3D 8 x 200 network) and
+    widths above 256 are refused with PINN_E_UNSUPPORTED; 32-point tiles are
+    refused above 8 row blocks."""
+    for dim, W, H, kw in [(3, 200, 8, {}), (2, 257, 2, {}), (2, 150, 2, {"tile_points": 32})]:
+        with pytest.raises(pkg.PinnError) as e:
+            pkg.context_from_problem(wl.tiny(dim=dim, width=W, depth=H), device="cuda", **kw)
+        assert "UNSUPPORTED" in str(e.value), (dim, W, H, str(e.value))

@@ -60,7 +60,7 @@ def test_size_query_rejects_bad_arguments_before_any_device_work():
     st = L.pinn_create(ctypes.byref(cfg), sub, None, ctypes.byref(n), None, None)
     assert st == abi.PINN_E_INVAL
     assert b"dim" in L.pinn_last_error()
-    cfg.dim, cfg.width = 2, 200
+    cfg.dim, cfg.width = 2, 257
     assert L.pinn_create(ctypes.byref(cfg), sub, None, ctypes.byref(n), None, None) == abi.PINN_E_UNSUPPORTED
     cfg.width, cfg.beta1, cfg.beta2, cfg.eps = 10, 0.9, 0.999, 1e-8
     # theta NULL
