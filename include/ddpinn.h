@@ -81,10 +81,10 @@ typedef enum {
 typedef struct {
   int32_t dim;            /* 2 or 3 spatial dimensions                        */
   int32_t width;          /* W, 1..256.  Above 128 each wave of a workgroup
-                             owns two 16-neuron row blocks.  A collocation
-                             tile must fit in LDS, else PINN_E_UNSUPPORTED:
-                             2D up to 176 at any depth (192 to depth 6), 3D up
-                             to 128 (144 to depth 5)                         */
+                             owns two 16-neuron row blocks; where the tile's
+                             activation stacks do not fit in LDS (2D above
+                             176, 3D above 144), the step keeps one forward
+                             stack and runs the backward over column halves */
   int32_t depth;          /* H hidden layers, 1..16                           */
   int32_t n_sub;          /* number of subdomains, 1..4096                    */
   int32_t activation;     /* 0 = tanh, 1 = sin (the paper's cylinder networks) */

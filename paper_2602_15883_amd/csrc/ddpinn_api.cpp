@@ -333,6 +333,10 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
     max_lds = std::max(max_lds, optin);
   HIPCHECK(ddp::set_lds_limits(max_lds));
 
+  // two row blocks per wave: the column-split LDS plan when the plain one
+  // does not fit
+  if (sh.NW > sh.NWV && (int64_t)step_lds_floats(sh, 16) * 4 > max_lds) c->sh.split = 1;
+
   // tile shape: 32-point collocation tiles when they fit in LDS with at
   // least the occupancy of 16-point tiles, unless fixed by the caller
   c->threads = sh.NWV * 64;

@@ -57,7 +57,8 @@ struct Shape {
   int32_t act;                    // activation: 0 tanh, 1 sin
   int32_t NWV;                    // waves per workgroup, min(NW, kMaxWaves): wave w owns row
                                   // block w and, when NW > kMaxWaves, row block w + NWV
-  int32_t pad_;
+  int32_t split;                  // two row blocks per wave and the step's LDS plan does not
+                                  // fit: one forward activation stack, backward by column halves
   // fragment buffer (per subdomain)
   int64_t f_hid;   // hidden layer l (2..H): forward A-fragments at f_hid + (l-2)*2*Wp*Wp,
                    // transposed (backward) A-fragments Wp*Wp further

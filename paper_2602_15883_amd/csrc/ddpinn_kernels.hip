@@ -444,6 +444,33 @@ __host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB) {
   return L;
 }
 
+// LDS plan of the column-split variant (two row blocks per wave, when the
+// plan above does not fit): the forward keeps one activation stack [NCOL][S]
+// at bufG; the backward holds Zbar [NCOL/2][S] at bufG and H_{l-1}
+// [Wp][NCOL/2 + 4] at bufH for one half of the tile's columns at a time.
+__host__ __device__ inline StepLds step_lds_split(int D, int Wp, int H, int NCB) {
+  StepLds L;
+  L.NCOL = 16 * NCB;
+  L.S = Wp + 4;
+  L.S2 = L.NCOL / 2 + 4;
+  const int zh = ((L.NCOL / 2) * L.S + 3) & ~3;
+  const int bwd = zh + Wp * L.S2;
+  const int fwd = L.NCOL * L.S;
+  int o = 0;
+  L.bufG = o;
+  L.bufH = o + zh;
+  o += ((fwd > bwd ? fwd : bwd) + 3) & ~3;
+  L.ys = o;   o += (D * L.NCOL + 3) & ~3;
+  L.yb = o;   o += (D * L.NCOL + 3) & ~3;
+  L.xin = o;  o += (L.NCOL * D + 3) & ~3;
+  L.acc1 = o; o += (Wp * D + 3) & ~3;
+  L.dbacc = o; o += (H * Wp + 3) & ~3;
+  L.red = o;  o += 64;
+  L.sched = o; o += 4;
+  L.total = o;
+  return L;
+}
+
 // ---------------------------------------------------------------------------
 // Backward pieces of one row block, for workgroups whose waves own two row
 // blocks (the one-row-block path runs the same steps inline)
@@ -510,6 +537,45 @@ __device__ __forceinline__ void adjoint_rows(v4f (&acc)[NCB], const v4f (&zs)[NC
   }
 }
 
+template <int SPLIT>
+__host__ __device__ inline StepLds step_plan(int D, int Wp, int H, int NCB) {
+  if constexpr (SPLIT) return step_lds_split(D, Wp, H, NCB);
+  else return step_lds(D, Wp, H, NCB);
+}
+
+// h = act(z) of a stashed pre-activation stack, only the column blocks
+// [CB0, CB0 + NCBH), written to the neuron-major LDS layout of that half
+template <int DIM, int NCB, int MODE, int ACT, int CB0, int NCBH>
+__device__ __forceinline__ void act_store_bwd_cols(float* buf, int S2, const v4f (&z)[NCB], int rb, int g, int j) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int NPB = M::NPB;
+  auto put = [](float* row, int cb, float v) {
+    if (cb >= CB0 && cb < CB0 + NCBH) row[16 * (cb - CB0)] = v;
+  };
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    float* row = buf + (16 * rb + 4 * g + i) * S2 + j;
+#pragma unroll
+    for (int pb = 0; pb < NPB; ++pb) {
+      if constexpr (MODE != M_PDE) {
+        if (pb < CB0 || pb >= CB0 + NCBH) continue;
+      }
+      float s, s1, s2;
+      act_d2<ACT>(z[pb][i], s, s1, s2);
+      put(row, pb, s);
+      if constexpr (MODE == M_PDE) {
+#pragma unroll
+        for (int jj = 0; jj <= DIM; ++jj) put(row, (1 + jj) * NPB + pb, s1 * z[(1 + jj) * NPB + pb][i]);
+#pragma unroll
+        for (int jj = 0; jj < DIM; ++jj) {
+          const float z1 = z[(1 + jj) * NPB + pb][i];
+          put(row, (DIM + 2 + jj) * NPB + pb, s2 * z1 * z1 + s1 * z[(DIM + 2 + jj) * NPB + pb][i]);
+        }
+      }
+    }
+  }
+}
+
 // dW_l += Zbar_l H_{l-1}^T for the rows of row block rb, into the layer's
 // block sw of the segment's slab; the old values are requested before each
 // chunk's GEMM so the read overlaps it
@@ -538,7 +604,7 @@ __device__ __forceinline__ void dw_rows(float* sw, bool first, const float* bufG
 // ---------------------------------------------------------------------------
 // Fused step kernel: persistent over this workgroup's item range.
 // ---------------------------------------------------------------------------
-template <int DIM, int PBP, int ACT, int RPW>
+template <int DIM, int PBP, int ACT, int RPW, int SPLIT>
 __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepArgs args) {
   constexpr int D = DIM + 1;
   constexpr int CF = 2 * DIM + 2;
@@ -556,7 +622,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   // lets every per-wave address (weights, stash, slab) be a scalar base plus
   // the lane offset instead of a 64-bit vector address per use
   const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, j = lane & 15;
-  const StepLds L = step_lds(D, Wp, H, NCB);
+  const StepLds L = step_plan<SPLIT>(D, Wp, H, NCB);
   float* bufH = lds + L.bufH;
   float* bufG = lds + L.bufG;
   float* ys = lds + L.ys;
@@ -684,6 +750,50 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         float* t = hin;
         hin = hout;
         hout = t;
+      }
+    } else if constexpr (SPLIT) {
+      // two row blocks per wave, one activation stack: every wave's GEMMs read
+      // the stack before any wave overwrites it; the first block's
+      // pre-activations wait in the stash meanwhile
+      hin = bufG;
+      for (int r = 0; r < nrb; ++r) {
+        const int rb = w + r * NWV;
+        float* st = stash_w + r * stash_rb;
+        if (pde) input_layer<DIM, NCB, M_PDE>(acc, W1p, bp, xin, rb, g, j);
+        else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, rb, g, j);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) stg4u(st + (0 * NCB + cb) * 256, lo16, acc[cb]);
+        if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
+        else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
+        store_fwd<NCB>(hin, S, acc, rb, g, j);
+      }
+      __syncthreads();
+      for (int l = 2; l <= H; ++l) {
+        for (int r = 0; r < nrb; ++r) {
+          const int rb = w + r * NWV;
+          float* st = stash_w + r * stash_rb;
+          const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)rb * 16 * Wp;
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+          if (w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
+          gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
+          __builtin_amdgcn_s_setprio(0);
+          if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, rb, g);
+          else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, rb, g);
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) stg4u(st + ((l - 1) * NCB + cb) * 256, lo16, acc[cb]);
+        }
+        __syncthreads();
+        for (int r = nrb - 1; r >= 0; --r) {
+          if (r != nrb - 1) {
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[cb] = ldg4u(stash_w + r * stash_rb + ((l - 1) * NCB + cb) * 256, lo16);
+          }
+          if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
+          else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
+          store_fwd<NCB>(hin, S, acc, w + r * NWV, g, j);
+        }
+        __syncthreads();
       }
     } else {
       // two row blocks per wave: the same steps per row block
@@ -988,11 +1098,76 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         out_adjoint_rows<D, NCB>(acc, Wop, yb, Wp, rb, g, j);
         if (pde) adjoint_rows<DIM, NCB, M_PDE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, H, g, j);
         else adjoint_rows<DIM, NCB, M_VALUE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, H, g, j);
-        if (H > 1 && r + 1 < nrb) {
+        if (H > 1 && (SPLIT || r + 1 < nrb)) {
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) stg4u(st + ((H - 1) * NCB + cb) * 256, lo16, acc[cb]);
         }
       }
+      if constexpr (SPLIT) {
+        // The tile's columns in two halves (Zbar and H_{l-1} of one half fit
+        // in LDS at a time; the GEMMs are separable over columns).  Every
+        // block's zbar and hbar wait in its own stash slot between barriers.
+        constexpr int NCBH = NCB / 2;
+        for (int l = H; l >= 2; --l) {
+          float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
+          const size_t zl = (size_t)(l - 1) * NCB * 256, zp = (size_t)(l - 2) * NCB * 256;
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh) {
+            __syncthreads();
+            v4f t[NCBH];
+            // Zbar_l of this half
+            for (int r = 0; r < nrb; ++r) {
+              const float* st = stash_w + r * stash_rb + zl + (size_t)hh * NCBH * 256;
+#pragma unroll
+              for (int c = 0; c < NCBH; ++c) t[c] = ldg4u(st + c * 256, lo16);
+              store_fwd<NCBH>(bufG, S, t, w + r * NWV, g, j);
+            }
+            // H_{l-1} of this half, recomputed from z_{l-1}
+            for (int r = 0; r < nrb; ++r) {
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(stash_w + r * stash_rb + zp + cb * 256, lo16);
+              if (hh == 0) {
+                if (pde) act_store_bwd_cols<DIM, NCB, M_PDE, ACT, 0, NCBH>(bufH, S2, zs, w + r * NWV, g, j);
+                else act_store_bwd_cols<DIM, NCB, M_VALUE, ACT, 0, NCBH>(bufH, S2, zs, w + r * NWV, g, j);
+              } else {
+                if (pde) act_store_bwd_cols<DIM, NCB, M_PDE, ACT, NCBH, NCBH>(bufH, S2, zs, w + r * NWV, g, j);
+                else act_store_bwd_cols<DIM, NCB, M_VALUE, ACT, NCBH, NCBH>(bufH, S2, zs, w + r * NWV, g, j);
+              }
+            }
+            __syncthreads();
+            if (raise) __builtin_amdgcn_s_setprio(2);
+            for (int r = 0; r < nrb; ++r)
+              dw_rows<NCBH>(sw, (item.flags & ITEM_FIRST) && hh == 0, bufG, S, bufH, S2, NW, w + r * NWV, g, j, lo16);
+            // Hbar_{l-1} of this half into the stash slot of Zbar_l (consumed)
+            for (int r = 0; r < nrb; ++r) {
+              const int rb = w + r * NWV;
+#pragma unroll
+              for (int c = 0; c < NCBH; ++c) t[c] = zero4();
+              const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)rb * 16 * Wp;
+              gemm_rows<NCBH>(WT, bufG, S, K4, g, j, lane, t);
+              float* st = stash_w + r * stash_rb + zl + (size_t)hh * NCBH * 256;
+#pragma unroll
+              for (int c = 0; c < NCBH; ++c) stg4u(st + c * 256, lo16, t[c]);
+            }
+            __builtin_amdgcn_s_setprio(0);
+          }
+          // adjoint of layer l-1 per block; zbar_{l-1} replaces z_{l-1}
+          for (int r = 0; r < nrb; ++r) {
+            const int rb = w + r * NWV;
+            float* st = stash_w + r * stash_rb;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[cb] = ldg4u(st + zl + cb * 256, lo16);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(st + zp + cb * 256, lo16);
+            if (pde) adjoint_rows<DIM, NCB, M_PDE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
+            else adjoint_rows<DIM, NCB, M_VALUE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
+            if (l > 2) {
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) stg4u(st + zp + cb * 256, lo16, acc[cb]);
+            }
+          }
+        }
+      } else {
       for (int l = H; l >= 2; --l) {
         __syncthreads();
         // Zbar_l into LDS: the last block's from registers, the first's from the stash
@@ -1035,6 +1210,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
             for (int cb = 0; cb < NCB; ++cb) stg4u(st + ((l - 2) * NCB + cb) * 256, lo16, acc[cb]);
           }
         }
+      }
       }
     }
 
@@ -1652,31 +1828,32 @@ int step_value_points(int dim, int tile_points) {
 
 int step_lds_floats(const Shape& sh, int tile_points) {
   const int NCB = (2 * sh.dim + 2) * (tile_points / 16);
-  return step_lds(sh.D, sh.Wp, sh.H, NCB).total;
+  return sh.split ? step_lds_split(sh.D, sh.Wp, sh.H, NCB).total : step_lds(sh.D, sh.Wp, sh.H, NCB).total;
 }
 
 int query_lds_floats(const Shape& sh) {
   return query_lds(sh.D, sh.Wp, 2 * sh.dim + 2).total;
 }
 
-// Kernel instances: dimension, tile (16 or 32 collocation points), activation
-// and row blocks per wave (2 above 8 row blocks; 16-point tiles only).
-static const void* step_ptr(int dim, int tile_points, int act, int rpw) {
+// Kernel instances: dimension, tile (16 or 32 collocation points), activation,
+// row blocks per wave (2 above 8 row blocks; 16-point tiles only) and, for two
+// row blocks, the column-split LDS plan.
+template <int DIM>
+static const void* step_ptr_dim(int tile_points, int act, int rpw, int split) {
   if (rpw == 2) {
-    if (dim == 2) return act == ACT_SIN ? (const void*)step_kernel<2, 1, ACT_SIN, 2> : (const void*)step_kernel<2, 1, ACT_TANH, 2>;
-    return act == ACT_SIN ? (const void*)step_kernel<3, 1, ACT_SIN, 2> : (const void*)step_kernel<3, 1, ACT_TANH, 2>;
+    if (split) return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 1> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 1>;
+    return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 0> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 0>;
   }
-  if (dim == 2) {
-    if (tile_points == 32) return act == ACT_SIN ? (const void*)step_kernel<2, 2, ACT_SIN, 1> : (const void*)step_kernel<2, 2, ACT_TANH, 1>;
-    return act == ACT_SIN ? (const void*)step_kernel<2, 1, ACT_SIN, 1> : (const void*)step_kernel<2, 1, ACT_TANH, 1>;
-  }
-  if (tile_points == 32) return act == ACT_SIN ? (const void*)step_kernel<3, 2, ACT_SIN, 1> : (const void*)step_kernel<3, 2, ACT_TANH, 1>;
-  return act == ACT_SIN ? (const void*)step_kernel<3, 1, ACT_SIN, 1> : (const void*)step_kernel<3, 1, ACT_TANH, 1>;
+  if (tile_points == 32) return act == ACT_SIN ? (const void*)step_kernel<DIM, 2, ACT_SIN, 1, 0> : (const void*)step_kernel<DIM, 2, ACT_TANH, 1, 0>;
+  return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 1, 0> : (const void*)step_kernel<DIM, 1, ACT_TANH, 1, 0>;
+}
+static const void* step_ptr(int dim, int tile_points, int act, int rpw, int split) {
+  return dim == 2 ? step_ptr_dim<2>(tile_points, act, rpw, split) : step_ptr_dim<3>(tile_points, act, rpw, split);
 }
 static int rows_per_wave(const Shape& sh) { return sh.NW > sh.NWV ? 2 : 1; }
 const void* step_kernel_ptr(const Shape& sh, int tile_points) {
   if (rows_per_wave(sh) == 2 && tile_points != 16) return nullptr;
-  return step_ptr(sh.dim, tile_points, sh.act, rows_per_wave(sh));
+  return step_ptr(sh.dim, tile_points, sh.act, rows_per_wave(sh), sh.split);
 }
 const void* prep_kernel_ptr() { return (const void*)prep_kernel; }
 const void* slab_sum_kernel_ptr() { return (const void*)slab_sum_kernel; }
@@ -1786,9 +1963,10 @@ hipError_t set_lds_limits(int bytes) {
   };
   for (int dim = 2; dim <= 3; ++dim)
     for (int act = ACT_TANH; act <= ACT_SIN; ++act) {
-      allow(step_ptr(dim, 16, act, 1));
-      allow(step_ptr(dim, 32, act, 1));
-      allow(step_ptr(dim, 16, act, 2));
+      allow(step_ptr(dim, 16, act, 1, 0));
+      allow(step_ptr(dim, 32, act, 1, 0));
+      allow(step_ptr(dim, 16, act, 2, 0));
+      allow(step_ptr(dim, 16, act, 2, 1));
       for (int rpw = 1; rpw <= 2; ++rpw) {
         for (int mode : {M_PDE, M_VALUE, M_GRAD}) allow(query_ptr(dim, mode, act, rpw));
         allow(exchange_ptr(dim, act, rpw));

@@ -1,9 +1,10 @@
 """Networks wider than 128 neurons: each wave of the step, query and exchange
 kernels then owns two 16-neuron row blocks (w and w + 8).  Cases span a wave
 mix of one and two blocks (W = 150: waves 0-1 hold two; W = 144 in 3D: wave 0),
-all waves with two (W = 192), padding (W = 129 -> 144), both activations, the
-paper's 2D-cylinder network width (6 x 150, sine; section 3.2, appendix B),
-several tiles per workgroup, and the limits of the LDS plan."""
+all waves with two (W = 192, 256), padding (W = 129 -> 144), both
+activations, the paper's cylinder networks (2D 6 x 150 and 3D 8 x 200, sine;
+sections 3.2-3.3, appendix B), the column-split LDS plan, several tiles per
+workgroup, the largest shape, and the limits."""
 import numpy as np
 import pytest
 
@@ -29,12 +30,20 @@ def act_oracle(orc):
     orc.set_activation("tanh")
 
 
-# dim, width, depth, activation, collocation points
+# dim, width, depth, activation, collocation points.  Where the two-block
+# LDS plan does not fit, the column-split plan runs (one forward activation
+# stack, backward by column halves): 2D above 192 (192 from depth 7), 3D
+# above 144 (144 from depth 6).
 WIDE = [(2, 150, 6, "sin", 87),      # the paper's 2D-cylinder network shape
         (2, 150, 2, "tanh", 8201),   # > 1 tile per workgroup: slab read-modify-write
         (2, 192, 2, "tanh", 87),     # every wave holds two row blocks
         (3, 144, 2, "tanh", 300),
-        (3, 129, 3, "sin", 50)]      # padded to 144
+        (3, 129, 3, "sin", 50),      # padded to 144
+        (3, 200, 8, "sin", 87),      # the paper's 3D-cylinder network shape (split)
+        (3, 200, 2, "tanh", 8201),   # split, > 1 tile per workgroup
+        (2, 192, 8, "tanh", 50),     # split
+        (2, 256, 2, "sin", 300),     # split, every wave two blocks
+        (3, 256, 16, "tanh", 40)]    # the largest shape: split plan at the LDS limit
 
 
 @pytest.mark.parametrize("dim,W,H,act,npde", WIDE)
@@ -105,10 +114,9 @@ def test_wide_routed_query_and_exchange(pkg, orc):
 
 
 def test_wide_limits(pkg):
-    """Tiles that do not fit in LDS (the paper's 3D 8 x 200 network) and
-    widths above 256 are refused with PINN_E_UNSUPPORTED; 32-point tiles are
-    refused above 8 row blocks."""
-    for dim, W, H, kw in [(3, 200, 8, {}), (2, 257, 2, {}), (2, 150, 2, {"tile_points": 32})]:
+    """Widths above 256 and depths above 16 are refused with
+    PINN_E_UNSUPPORTED, and so are 32-point tiles above 8 row blocks."""
+    for dim, W, H, kw in [(3, 257, 2, {}), (2, 64, 17, {}), (2, 150, 2, {"tile_points": 32})]:
         with pytest.raises(pkg.PinnError) as e:
             pkg.context_from_problem(wl.tiny(dim=dim, width=W, depth=H), device="cuda", **kw)
         assert "UNSUPPORTED" in str(e.value), (dim, W, H, str(e.value))
