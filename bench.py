@@ -43,6 +43,8 @@ WORKLOADS = {
     "config3": "config3_16x2d_6x64",
     "config4": "config4_3d_8x128_250k",
     "cylinder3d": "cylinder3d_recipe_3d_8x128_250k_sin",
+    "cylinder2d_paper": "cylinder2d_paper_2d_6x150_500k_sin",
+    "cylinder3d_paper": "cylinder3d_paper_3d_8x200_600k_sin",
 }
 
 
@@ -77,7 +79,8 @@ def algorithmic_bytes(pb):
 def make_problem(name, seed=0):
     import workloads as wl
     return {"config1": wl.config1, "config2": wl.config2, "config3": wl.config3,
-            "config4": wl.config4, "cylinder3d": wl.cylinder3d_recipe}[name](seed)
+            "config4": wl.config4, "cylinder3d": wl.cylinder3d_recipe,
+            "cylinder2d_paper": wl.cylinder2d_paper, "cylinder3d_paper": wl.cylinder3d_paper}[name](seed)
 
 
 def kernel_source_hash():

@@ -392,3 +392,74 @@ def cylinder3d_recipe(seed: int = 0, n_pde: int = 250_000, n_obs: int = 20_000,
     pb.lr_factor = 0.3
     pb.lr_interval = 5000
     return pb
+
+
+def _outside_cylinder(rng, n, lo, hi, radius=0.5):
+    """n points uniform in the box [lo, hi) with (x, y) outside the cylinder
+    of the given radius centred at the origin (rejection sampling)."""
+    out = np.zeros((0, len(lo)), np.float32)
+    while out.shape[0] < n:
+        x = uniform(rng, 2 * (n - out.shape[0]) + 64, lo, hi)
+        keep = x[:, 0].astype(np.float64) ** 2 + x[:, 1].astype(np.float64) ** 2 >= radius * radius
+        out = np.concatenate([out, x[keep]])
+    return np.ascontiguousarray(out[:n])
+
+
+def _snapshot_points(rng, n_snap, per_snap, lo, hi, dt=0.15):
+    """per_snap spatial locations (outside the cylinder) at each of n_snap
+    snapshot times t_k = k dt."""
+    D = len(lo)
+    xs = _outside_cylinder(rng, n_snap * per_snap, list(lo[:-1]) + [0.0], list(hi[:-1]) + [1.0])
+    xs[:, D - 1] = np.repeat(np.arange(n_snap) * dt, per_snap).astype(np.float32)
+    return xs
+
+
+def cylinder2d_paper(seed: int = 0) -> Problem:
+    """The paper's 2D cylinder-wake training problem on one GPU (section 3.2,
+    appendix B, P = 1): 3 -> 6x150 sin -> 3 on [-7.5, 17.5] x [-8, 8] x
+    [0, 7.35] with the cylinder r < 0.5 cut out; 500,000 collocation points;
+    10,000 velocity observations (200 locations at each of 50 snapshots,
+    dt = 0.15); weights (obs, PDE) = (10, 5); Re = 100; learning rate 1e-3
+    decayed by 0.2 every 2,000 steps.  The CFD data are not available: the
+    observed velocities come from the Fourier stream field."""
+    rng = np.random.default_rng([seed, 21])
+    lo, hi = np.array([-7.5, -8.0, 0.0]), np.array([17.5, 8.0, 7.35])
+    f = FourierStream(seed, nu=0.01)
+    th = xavier_theta(2, 150, 6, seed)
+    pde = _outside_cylinder(rng, 500_000, lo, hi)
+    obs = _snapshot_points(rng, 50, 200, lo, hi)
+    u, v = f.uv(obs[:, 0] / 8.0, obs[:, 1] / 8.0, obs[:, 2])
+    s = _sub(2, lo, hi, th, pde_x=pde, obs_x=obs, obs_u=np.stack([u, v], 1).astype(np.float32))
+    lam = np.array([10.0, 5.0, 1.0, 1.0, 1.0, 0.0])
+    pb = Problem("cylinder2d_paper_2d_6x150_500k_sin", 2, 150, 6, 1.0 / 100.0, lam, 1e-3, [s])
+    pb.activation = "sin"
+    pb.lr_factor, pb.lr_interval = 0.2, 2000
+    return pb
+
+
+def cylinder3d_paper(seed: int = 0) -> Problem:
+    """The paper's 3D cylinder-wake training problem on one GPU (section 3.3,
+    appendix B, P = 1): 4 -> 8x200 sin -> 4 on [-5, 20] x [-5, 5] x [0, 10] x
+    [0, 11.85] with the cylinder r < 0.5 cut out; 600,000 collocation points;
+    100,000 velocity observations (1,250 locations at each of 80 snapshots,
+    dt = 0.15); weights (obs, PDE) = (10, 10); velocity-component weights
+    (1, 5, 100); global-norm clipping at 1.0; Re = 300; learning rate 1e-3
+    decayed by 0.3 every 5,000 steps.  The CFD data are not available: the
+    observed velocities come from the Ethier-Steinman field on coordinates
+    mapped to [-1, 1]^3 x [0, 1]."""
+    rng = np.random.default_rng([seed, 22])
+    lo, hi = np.array([-5.0, -5.0, 0.0, 0.0]), np.array([20.0, 5.0, 10.0, 11.85])
+    th = xavier_theta(3, 200, 8, seed)
+    pde = _outside_cylinder(rng, 600_000, lo, hi)
+    obs = _snapshot_points(rng, 80, 1250, lo, hi)
+    xm = [2.0 * (obs[:, i].astype(np.float64) - lo[i]) / (hi[i] - lo[i]) - 1.0 for i in range(3)]
+    u, v, w, _ = ethier_steinman(*xm, obs[:, 3].astype(np.float64) / hi[3])
+    s = _sub(3, lo, hi, th, pde_x=pde, obs_x=obs, obs_u=np.stack([u, v, w], 1).astype(np.float32))
+    lam = np.array([10.0, 10.0, 1.0, 1.0, 1.0, 0.0])
+    pb = Problem("cylinder3d_paper_3d_8x200_600k_sin", 3, 200, 8, 1.0 / 300.0, lam, 1e-3, [s])
+    pb.activation = "sin"
+    pb.comp_w = np.array([1.0, 5.0, 100.0])
+    pb.clip_norm = 1.0
+    pb.lr_factor, pb.lr_interval = 0.3, 5000
+    return pb
+
