@@ -106,21 +106,20 @@ def traffic_from_profiles(workload):
     return e.get("bytes_per_launch")
 
 
-def cpu_baseline(pb, budget_s=12.0):
+def cpu_baseline(pb, budget_s=12.0, one_core_s=5.0):
     """FP64 oracle (loss + gradient [+ clipping] + Adam) on a bounded sample of
     the workload, sized to roughly budget_s seconds from a short calibration
     run: a prefix of the collocation points with the same per-point mix of
     observation and ghost points, repeated over several steps when the whole
     workload takes less than the budget.  Same activation and component
-    weights as the workload."""
+    weights as the workload.  Timed on all the host cores the oracle uses,
+    then on one core (a smaller sample of about one_core_s seconds)."""
     import oracle
     cores = oracle.threads(0)
     s = pb.subs[0]
     n_all = s.pde_x.shape[0]
     frac_obs = s.obs_x.shape[0] / max(n_all, 1)
     frac_gh = s.gh_x.shape[0] / max(n_all, 1)
-    oracle.set_activation(pb.activation)
-    oracle.set_component_weights(pb.comp_w)
 
     def run(n, reps=1):
         no, ng = int(round(n * frac_obs)), int(round(n * frac_gh))
@@ -135,22 +134,32 @@ def cpu_baseline(pb, budget_s=12.0):
             oracle.adam(s.theta, np.zeros(g.size), np.zeros(g.size), g, 1, lr=pb.lr)
         return time.perf_counter() - t0, no, ng
 
-    try:
+    def measure(budget):
         n0 = min(n_all, 256)
         t0, _, _ = run(n0)
-        n = int(min(n_all, max(n0, n0 * budget_s / max(t0, 1e-3))))
+        n = int(min(n_all, max(n0, n0 * budget / max(t0, 1e-3))))
         reps = 1
         if n == n_all:
             t_all, _, _ = run(n_all)
-            reps = max(1, int(round(budget_s / max(t_all, 1e-3))))
+            reps = max(1, int(round(budget / max(t_all, 1e-3))))
         dt, no, ng = run(n, reps)
+        return (n * reps / dt,
+                (f"first {n} of {n_all} collocation points of subdomain 0 with {no} observation and "
+                 f"{ng} ghost points (same per-point mix), {reps} step(s): FP64 loss, gradient and "
+                 f"Adam, {pb.activation} network, {dt:.1f} s"))
+
+    oracle.set_activation(pb.activation)
+    oracle.set_component_weights(pb.comp_w)
+    try:
+        value, sample = measure(budget_s)
+        oracle.threads(1)
+        v1, s1 = measure(one_core_s)
     finally:
+        oracle.threads(cores)
         oracle.set_activation("tanh")
         oracle.set_component_weights(None)
-    return {"value": n * reps / dt, "unit": "collocation pts/s", "cores": cores, "kind": "oracle",
-            "sample": (f"first {n} of {n_all} collocation points of subdomain 0 with {no} "
-                       f"observation and {ng} ghost points (same per-point mix), {reps} step(s): "
-                       f"FP64 loss, gradient and Adam, {pb.activation} network, {dt:.1f} s")}
+    return {"value": value, "unit": "collocation pts/s", "cores": cores, "kind": "oracle", "sample": sample,
+            "one_core": {"value": v1, "unit": "collocation pts/s", "cores": 1, "sample": s1}}
 
 
 def query_bench(seconds, seed=0, rate=200.0, budget=32 << 30):
@@ -295,8 +304,21 @@ def main():
     loss = ctx._loss.cpu().numpy()
     finite = bool(np.all(np.isfinite(loss)))
 
-    # ---- roofline: HIP events around the fused kernel launches, same workload
+    # ---- per-step distribution: HIP events around each graph replay (the whole
+    # step: prep, fused kernel, reduction, Adam), a separate pass
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     base_t = args.warmup + args.steps
+    for k, (e0, e1) in enumerate(evs):
+        e0.record()
+        ctx.step(base_t + 1 + k)
+        e1.record()
+    torch.cuda.synchronize()
+    st = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
+    step_ms = {"p10": float(np.percentile(st, 10)), "p50": float(np.median(st)),
+               "p90": float(np.percentile(st, 90)), "steps": int(st.size)}
+
+    # ---- roofline: HIP events around the fused kernel launches, same workload
+    base_t = args.warmup + 2 * args.steps
     ctx.kernel_time()
     for k in range(args.steps):
         ctx.step(base_t + 1 + k, time_kernel=True)
@@ -340,6 +362,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_per_step,
+        "step_ms": step_ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
