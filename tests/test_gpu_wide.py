@@ -75,6 +75,29 @@ def test_wide_loss_grad_channels(pkg, act_oracle, dim, W, H, act, npde):
         ctx.close()
 
 
+@pytest.mark.parametrize("W,H", [(150, 2), (200, 2)])
+def test_wide_grouped_equals_per_subdomain_and_oracle(pkg, orc, W, H):
+    """16 wide subdomains of uneven size (masters, ghost faces of both kinds,
+    the anchor term) in one grouped launch and in plain per-subdomain
+    launches; W = 200 in 2D takes the column-split plan."""
+    pb = wl.config3(1, width=W, depth=H, pde_range=(40, 700), n_obs=30, n_gh_face=20)
+    print(f"wide grouped W={W} H={H}", flush=True)
+    ctx = pkg.context_from_problem(pb, device="cuda", graph=True)
+    try:
+        loss, g = ctx.step(1, update=False, want_grad=True)
+        loss2, g2 = ctx.step(1, update=False, want_grad=True, per_subdomain=True)
+        torch.cuda.synchronize()
+        L, G, L2, G2 = (t.cpu().numpy().astype(np.float64) for t in (loss, g, loss2, g2))
+    finally:
+        ctx.close()
+    for s in range(len(pb.subs)):
+        Lr, gr = oracle_loss_grad(orc, pb, sub=s)
+        assert_close(L[s], Lr, TOL_LOSS, f"loss sub {s}")
+        assert_close(G[s], gr, TOL_GRAD, f"grad sub {s}")
+        assert_close(L2[s], Lr, TOL_LOSS, f"per-sub loss sub {s}")
+        assert_close(G2[s], gr, TOL_GRAD, f"per-sub grad sub {s}")
+
+
 def test_wide_routed_query_and_exchange(pkg, orc):
     W, H = 150, 2
     boxes, thetas = wl.serving_nets(seed=5, width=W, depth=H)
@@ -120,3 +143,23 @@ def test_wide_limits(pkg):
         with pytest.raises(pkg.PinnError) as e:
             pkg.context_from_problem(wl.tiny(dim=dim, width=W, depth=H), device="cuda", **kw)
         assert "UNSUPPORTED" in str(e.value), (dim, W, H, str(e.value))
+
+
+def test_wide_training_loop_reduces_loss(pkg):
+    """The domain-decomposed loop (steps, exchange every second step, Adam)
+    on four 2D subdomains of width 150 (two row blocks per wave)."""
+    from paper_2602_15883_amd.trainer import DDTrainer, faces_of
+    pb = wl.config3(2, pde_range=(500, 900), n_obs=200, n_gh_face=50, K=2, M=2, width=150, depth=2)
+    print("wide training loop", flush=True)
+    ctx = pkg.context_from_problem(pb, device="cuda", graph=True)
+    try:
+        tr = DDTrainer(ctx, faces_of(pb), pb.x_anc, i_comm=2)
+        first = tr.step().cpu().numpy()[:, 6].copy()
+        for _ in range(150):
+            last = tr.step()
+        last = last.cpu().numpy()[:, 6]
+    finally:
+        ctx.close()
+    assert np.all(np.isfinite(last))
+    assert last.sum() < 0.8 * first.sum()
+
