@@ -57,6 +57,7 @@ Shape make_shape(int dim, int W, int H) {
   sh.Wp = (W + 15) / 16 * 16;
   sh.NW = sh.Wp / 16;
   sh.NWV = std::min(sh.NW, kMaxWaves);
+  sh.Kq = (W + 3) / 4;
   sh.P = (int32_t)nparams(dim, W, H);
   const int64_t Wp = sh.Wp, D = sh.D;
   // packed offsets

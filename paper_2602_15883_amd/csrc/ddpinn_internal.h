@@ -59,6 +59,9 @@ struct Shape {
                                   // block w and, when NW > kMaxWaves, row block w + NWV
   int32_t split;                  // two row blocks per wave and the step's LDS plan does not
                                   // fit: one forward activation stack, backward by column halves
+  int32_t Kq;                     // ceil(W/4): K-steps of the hidden-layer GEMMs (hidden neurons
+                                  // are stored at permuted positions, see hid_pos)
+  int32_t pad_;
   // fragment buffer (per subdomain)
   int64_t f_hid;   // hidden layer l (2..H): forward A-fragments at f_hid + (l-2)*2*Wp*Wp,
                    // transposed (backward) A-fragments Wp*Wp further

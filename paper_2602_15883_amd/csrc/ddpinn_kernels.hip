@@ -263,23 +263,49 @@ __device__ __forceinline__ void mfma_step(const v4f a, const float* bb, int S, i
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[q], b[cb][q], acc[cb]);
 }
 
+// the last, partial chunk: only its first KT K-steps hold neurons
+template <int NCB>
+__device__ __forceinline__ void mfma_tail(const v4f a, const float* bb, int S, int s4, int KT, v4f (&acc)[NCB]) {
+  v4f b[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const v4f*>(bb + cb * 16 * S + 4 * s4);
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[0], b[cb][0], acc[cb]);
+  if (KT > 1) {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[1], b[cb][1], acc[cb]);
+  }
+  if (KT > 2) {
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[2], b[cb][2], acc[cb]);
+  }
+}
+
+// K = 4*K4 + KT steps: K4 full chunks of four, then KT (0..3) more
 template <int NCB>
 __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const float* bufB,
                                           int S, int K4, int g, int j, int lane,
-                                          v4f (&acc)[NCB]) {
-  const float* bb = bufB + j * S + g * (4 * K4);
+                                          v4f (&acc)[NCB], int KT) {
+  const int KC = K4 + (KT ? 1 : 0);   // chunks per row block (4*KC = Wp/4, a lane group's segment)
+  const float* bb = bufB + j * S + g * (4 * KC);
   const uint32_t lo = (uint32_t)lane * 16u;
-  // two weight-fragment registers: the fragment of the next step is in
-  // flight while the MFMAs of the current step run
+  // two weight-fragment registers: the fragment of the next chunk is in
+  // flight while the MFMAs of the current one run
   v4f a0 = ldg4u(afrag, lo);
   int s4 = 0;
   for (; s4 + 2 <= K4; s4 += 2) {
     const v4f a1 = ldg4u(afrag + (s4 + 1) * 256, lo);
     mfma_step<NCB>(a0, bb, S, s4, acc);
-    a0 = ldg4u(afrag + (s4 + 2 < K4 ? s4 + 2 : s4 + 1) * 256, lo);
+    a0 = ldg4u(afrag + (s4 + 2 < KC ? s4 + 2 : s4 + 1) * 256, lo);
     mfma_step<NCB>(a1, bb, S, s4 + 1, acc);
   }
-  if (s4 < K4) mfma_step<NCB>(a0, bb, S, s4, acc);
+  if (s4 < K4) {
+    const v4f a1 = KT ? ldg4u(afrag + (s4 + 1) * 256, lo) : a0;
+    mfma_step<NCB>(a0, bb, S, s4, acc);
+    a0 = a1;
+    ++s4;
+  }
+  if (KT) mfma_tail<NCB>(a0, bb, S, s4, KT, acc);
 }
 
 // dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col], t < NNB
@@ -616,7 +642,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
 
   const Shape& sh = args.sh;
   const int Wp = sh.Wp, NW = sh.NW, NWV = sh.NWV, H = sh.H;
-  const int K4 = Wp / 16;
+  const int K4 = sh.Kq >> 2, KT = sh.Kq & 3;   // K-steps of the hidden GEMMs: 4*K4 + KT
   const int tid = threadIdx.x, nthr = blockDim.x;
   // the wave index is uniform across a wave: keeping it in a scalar register
   // lets every per-wave address (weights, stash, slab) be a scalar base plus
@@ -737,7 +763,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         // the older one, which then idles at the next barrier while the younger
         // finishes.  Raising the younger half's priority for the GEMM evens them.
         if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-        gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
+        gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc, KT);
         __builtin_amdgcn_s_setprio(0);
         if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, g);
         else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
@@ -776,7 +802,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
           if (w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
-          gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
+          gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc, KT);
           __builtin_amdgcn_s_setprio(0);
           if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, rb, g);
           else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, rb, g);
@@ -817,7 +843,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
           if (w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
-          gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc);
+          gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc, KT);
           __builtin_amdgcn_s_setprio(0);
           if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, rb, g);
           else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, rb, g);
@@ -1056,7 +1082,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
           const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
           if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-          gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc);
+          gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc, KT);
           __builtin_amdgcn_s_setprio(0);
         }
       }
@@ -1144,7 +1170,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
 #pragma unroll
               for (int c = 0; c < NCBH; ++c) t[c] = zero4();
               const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)rb * 16 * Wp;
-              gemm_rows<NCBH>(WT, bufG, S, K4, g, j, lane, t);
+              gemm_rows<NCBH>(WT, bufG, S, K4, g, j, lane, t, KT);
               float* st = stash_w + r * stash_rb + zl + (size_t)hh * NCBH * 256;
 #pragma unroll
               for (int c = 0; c < NCBH; ++c) stg4u(st + c * 256, lo16, t[c]);
@@ -1201,7 +1227,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
           const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)rb * 16 * Wp;
           if (raise) __builtin_amdgcn_s_setprio(2);
-          gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc);
+          gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc, KT);
           __builtin_amdgcn_s_setprio(0);
           if (pde) adjoint_rows<DIM, NCB, M_PDE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
           else adjoint_rows<DIM, NCB, M_VALUE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
@@ -1246,7 +1272,22 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
 }
 
 // ---------------------------------------------------------------------------
-// prep: fragment-ordered copies of the weights (zero padded to Wp)
+// Hidden-neuron positions.  A hidden layer's Wp positions are read by the four
+// lane groups of a GEMM's K dimension in segments of Wp/4.  Neuron n sits at
+// position (n / Kq) * (Wp/4) + n % Kq with Kq = ceil(W/4): the padding fills
+// the tail of every segment, so the GEMMs stop after Kq K-steps instead of
+// Wp/4.  This is a permutation of the hidden neurons with zero weights at the
+// padded positions (whose activations are 0), so the network is unchanged.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline int hid_pos(const Shape& sh, int n) { return (n / sh.Kq) * (sh.Wp / 4) + n % sh.Kq; }
+__host__ __device__ inline int hid_neuron(const Shape& sh, int p) {
+  const int seg = sh.Wp / 4, g = p / seg, s = p - g * seg, n = g * sh.Kq + s;
+  return (s < sh.Kq && n < sh.W) ? n : -1;
+}
+
+// ---------------------------------------------------------------------------
+// prep: fragment-ordered copies of the weights (hidden neurons at their
+// positions, zeros at padded positions)
 // ---------------------------------------------------------------------------
 __global__ void prep_kernel(const PrepArgs a) {
   const Shape& sh = a.sh;
@@ -1267,18 +1308,18 @@ __global__ void prep_kernel(const PrepArgs a) {
     const int q = e & 3, lane = (e >> 2) & 63, t = e >> 8;
     const int K4 = Wp / 16;
     const int s4 = t % K4, w = t / K4;
-    const int k = (lane >> 4) * (Wp / 4) + 4 * s4 + q;
-    const int r = 16 * w + (lane & 15);
-    if (r < W && k < W) v = trans ? th[sh.p_w[l] + (int64_t)k * W + r] : th[sh.p_w[l] + (int64_t)r * W + k];
+    const int k = hid_neuron(sh, (lane >> 4) * (Wp / 4) + 4 * s4 + q);
+    const int r = hid_neuron(sh, 16 * w + (lane & 15));
+    if (r >= 0 && k >= 0) v = trans ? th[sh.p_w[l] + (int64_t)k * W + r] : th[sh.p_w[l] + (int64_t)r * W + k];
   } else if (idx < sh.f_b) {
-    const int e = (int)(idx - sh.f_w1), r = e / D, q = e - r * D;
-    if (r < W) v = th[sh.p_w[1] + (int64_t)r * D + q];
+    const int e = (int)(idx - sh.f_w1), p = e / D, q = e - p * D, r = hid_neuron(sh, p);
+    if (r >= 0) v = th[sh.p_w[1] + (int64_t)r * D + q];
   } else if (idx < sh.f_wo) {
-    const int e = (int)(idx - sh.f_b), l = 1 + e / Wp, r = e % Wp;
-    if (r < W) v = th[sh.p_b[l] + r];
+    const int e = (int)(idx - sh.f_b), l = 1 + e / Wp, r = hid_neuron(sh, e % Wp);
+    if (r >= 0) v = th[sh.p_b[l] + r];
   } else if (idx < sh.f_bo) {
-    const int e = (int)(idx - sh.f_wo), o = e / Wp, n = e % Wp;
-    if (n < W) v = th[sh.p_w[H + 1] + (int64_t)o * W + n];
+    const int e = (int)(idx - sh.f_wo), o = e / Wp, n = hid_neuron(sh, e % Wp);
+    if (n >= 0) v = th[sh.p_w[H + 1] + (int64_t)o * W + n];
   } else if (idx < sh.f_bo + 4) {
     const int o = (int)(idx - sh.f_bo);
     if (o < D) v = th[sh.p_b[H + 1] + o];
@@ -1293,24 +1334,25 @@ __device__ __forceinline__ int64_t slab_pos(const Shape& sh, int64_t p) {
   const int W = sh.W, Wp = sh.Wp, D = sh.D, H = sh.H;
   if (p < sh.p_b[1]) {                        // W1 [W][D]
     const int64_t r = p / D, q = p - r * D;
-    return sh.s_w1 + r * D + q;
+    return sh.s_w1 + (int64_t)hid_pos(sh, (int)r) * D + q;
   }
   if (p < sh.p_w[2 <= H ? 2 : H + 1]) {       // b1
-    return sh.s_b + (p - sh.p_b[1]);
+    return sh.s_b + hid_pos(sh, (int)(p - sh.p_b[1]));
   }
   for (int l = 2; l <= H; ++l) {
     if (p < sh.p_b[l]) {                      // W_l [W][W] in accumulator order
       const int64_t e = p - sh.p_w[l];
-      const int r = (int)(e / W), c = (int)(e - (int64_t)r * W);
+      const int r0 = (int)(e / W), c0 = (int)(e - (int64_t)r0 * W);
+      const int r = hid_pos(sh, r0), c = hid_pos(sh, c0);
       const int w = r >> 4, g = (r & 15) >> 2, i = r & 3, nb = c >> 4, jj = c & 15;
       return sh.s_hid + (int64_t)(l - 2) * Wp * Wp + ((int64_t)(w * sh.NW + nb) * 64 + g * 16 + jj) * 4 + i;
     }
-    if (p < sh.p_w[l + 1]) return sh.s_b + (int64_t)(l - 1) * Wp + (p - sh.p_b[l]);
+    if (p < sh.p_w[l + 1]) return sh.s_b + (int64_t)(l - 1) * Wp + hid_pos(sh, (int)(p - sh.p_b[l]));
   }
   if (p < sh.p_b[H + 1]) {                    // W_{H+1} [D][W]
     const int64_t e = p - sh.p_w[H + 1];
     const int o = (int)(e / W), n = (int)(e - (int64_t)o * W);
-    return sh.s_wo + (int64_t)o * Wp + n;
+    return sh.s_wo + (int64_t)o * Wp + hid_pos(sh, n);
   }
   return sh.s_bo + (p - sh.p_b[H + 1]);
 }
@@ -1513,7 +1555,7 @@ __device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, f
                                              const float* xin, int S, int tid, int nthr, int w, int g,
                                              int j, int lane) {
   using M = ModeCfg<DIM, NCB, MODE>;
-  const int Wp = sh.Wp, H = sh.H, K4 = Wp / 16, NWV = sh.NWV;
+  const int Wp = sh.Wp, H = sh.H, K4 = sh.Kq >> 2, KT = sh.Kq & 3, NWV = sh.NWV;
   const int nrb = (RPW == 1) ? 1 : (w + NWV < sh.NW ? 2 : 1);
   v4f acc[RPW][NCB];
 #pragma unroll
@@ -1532,7 +1574,7 @@ __device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, f
       const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)rb * 16 * Wp;
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = zero4();
-      gemm_rows<NCB>(Wf, bufH, S, K4, g, j, lane, acc[r]);
+      gemm_rows<NCB>(Wf, bufH, S, K4, g, j, lane, acc[r], KT);
       add_bias<NCB, M::NPB>(acc[r], fr + sh.f_b + (l - 1) * Wp, rb, g);
     }
     __syncthreads();
