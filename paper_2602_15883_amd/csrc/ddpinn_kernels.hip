@@ -1194,49 +1194,50 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           }
         }
       } else {
-      for (int l = H; l >= 2; --l) {
-        __syncthreads();
-        // Zbar_l into LDS: the last block's from registers, the first's from the stash
-        store_fwd<NCB>(bufG, S, acc, w + (nrb - 1) * NWV, g, j);
-        if (nrb == 2) {
+        // every block's Zbar_l and H_{l-1} fit in LDS together
+        for (int l = H; l >= 2; --l) {
+          __syncthreads();
+          // Zbar_l into LDS: the last block's from registers, the first's from the stash
+          store_fwd<NCB>(bufG, S, acc, w + (nrb - 1) * NWV, g, j);
+          if (nrb == 2) {
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) acc[cb] = ldg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16);
-          store_fwd<NCB>(bufG, S, acc, w, g, j);
-        }
-        // h_{l-1} recomputed from z_{l-1}
-        for (int r = 0; r < nrb; ++r) {
+            for (int cb = 0; cb < NCB; ++cb) acc[cb] = ldg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16);
+            store_fwd<NCB>(bufG, S, acc, w, g, j);
+          }
+          // h_{l-1} recomputed from z_{l-1}
+          for (int r = 0; r < nrb; ++r) {
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb)
-            zs[cb] = ldg4u(stash_w + r * stash_rb + ((l - 2) * NCB + cb) * 256, lo16);
-          if (pde) act_store_bwd<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w + r * NWV, g, j);
-          else act_store_bwd<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w + r * NWV, g, j);
-        }
-        __syncthreads();
-        float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
-        if (raise) __builtin_amdgcn_s_setprio(2);
-        for (int r = 0; r < nrb; ++r)
-          dw_rows<NCB>(sw, item.flags & ITEM_FIRST, bufG, S, bufH, S2, NW, w + r * NWV, g, j, lo16);
-        __builtin_amdgcn_s_setprio(0);
-        // Hbar_{l-1} = W_l^T Zbar_l, then the adjoint of layer l-1, per block
-        for (int r = 0; r < nrb; ++r) {
-          const int rb = w + r * NWV;
-          float* st = stash_w + r * stash_rb;
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(st + ((l - 2) * NCB + cb) * 256, lo16);
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
-          const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)rb * 16 * Wp;
+            for (int cb = 0; cb < NCB; ++cb)
+              zs[cb] = ldg4u(stash_w + r * stash_rb + ((l - 2) * NCB + cb) * 256, lo16);
+            if (pde) act_store_bwd<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w + r * NWV, g, j);
+            else act_store_bwd<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w + r * NWV, g, j);
+          }
+          __syncthreads();
+          float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
           if (raise) __builtin_amdgcn_s_setprio(2);
-          gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc, KT);
+          for (int r = 0; r < nrb; ++r)
+            dw_rows<NCB>(sw, item.flags & ITEM_FIRST, bufG, S, bufH, S2, NW, w + r * NWV, g, j, lo16);
           __builtin_amdgcn_s_setprio(0);
-          if (pde) adjoint_rows<DIM, NCB, M_PDE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
-          else adjoint_rows<DIM, NCB, M_VALUE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
-          if (l > 2 && r + 1 < nrb) {
+          // Hbar_{l-1} = W_l^T Zbar_l, then the adjoint of layer l-1, per block
+          for (int r = 0; r < nrb; ++r) {
+            const int rb = w + r * NWV;
+            float* st = stash_w + r * stash_rb;
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) stg4u(st + ((l - 2) * NCB + cb) * 256, lo16, acc[cb]);
+            for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(st + ((l - 2) * NCB + cb) * 256, lo16);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+            const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)rb * 16 * Wp;
+            if (raise) __builtin_amdgcn_s_setprio(2);
+            gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc, KT);
+            __builtin_amdgcn_s_setprio(0);
+            if (pde) adjoint_rows<DIM, NCB, M_PDE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
+            else adjoint_rows<DIM, NCB, M_VALUE, ACT>(acc, zs, dbacc, acc1, xin, Wp, rb, l - 1, g, j);
+            if (l > 2 && r + 1 < nrb) {
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) stg4u(st + ((l - 2) * NCB + cb) * 256, lo16, acc[cb]);
+            }
           }
         }
-      }
       }
     }
 
