@@ -49,8 +49,11 @@ def check_channels(P, ctx, orc, pb, x, sub=0, label=""):
     assert_close(r, rref, TOL_RESIDUAL, f"{label} residuals")
 
 
+# widths cover every tail of the hidden GEMMs' K loop (ceil(W/4) mod 4 = 0..3) and a loop
+# with no full chunk of four K-steps (W = 5, 12)
 TINY = [(2, 5, 2, 7, 5, 4, 2), (3, 5, 3, 19, 9, 6, 1), (2, 20, 1, 33, 0, 0, 0),
-        (2, 16, 2, 16, 3, 0, 2), (3, 33, 2, 40, 100, 130, 3), (2, 50, 3, 1, 1, 1, 1)]
+        (2, 16, 2, 16, 3, 0, 2), (3, 33, 2, 40, 100, 130, 3), (2, 50, 3, 1, 1, 1, 1),
+        (2, 28, 3, 37, 5, 4, 2), (3, 12, 2, 23, 7, 3, 1)]
 
 
 @pytest.mark.parametrize("dim,W,H,npde,nobs,ngh,nanc", TINY)
