@@ -229,6 +229,51 @@ def test_empty_sets_and_single_points(pkg, orc):
     ctx.close()
 
 
+def test_many_subdomains_some_empty(pkg, orc):
+    """300 small subdomains in one grouped launch, of very uneven size; every
+    tenth has no points at all (its losses and gradient are exactly 0), others
+    have only collocation, only value or single points.  Each equals the
+    oracle, and the grouped launch equals plain per-subdomain launches."""
+    rng = np.random.default_rng(17)
+    dim, W, H = 2, 16, 2
+    lo, hi = np.zeros(3), np.ones(3)
+    subs = []
+    for k in range(300):
+        if k % 10 == 0:
+            n = (0, 0, 0, 0)
+        else:
+            n = (int(rng.choice([0, 1, 5, 17, 40, 130])), int(rng.choice([0, 1, 3, 97])),
+                 int(rng.choice([0, 2])), int(rng.choice([0, 1])))
+        th = wl.xavier_theta(dim, W, H, k) + (0.05 * rng.standard_normal(wl.n_params(dim, W, H))).astype(np.float32)
+        subs.append(wl._sub(dim, lo, hi, th.astype(np.float32), is_master=bool(k % 7 == 0),
+                            pde_x=wl.uniform(rng, n[0], lo, hi), obs_x=wl.uniform(rng, n[1], lo, hi),
+                            obs_u=rng.standard_normal((n[1], dim)).astype(np.float32),
+                            gh_x=wl.uniform(rng, n[2], lo, hi),
+                            gh_up=rng.standard_normal((n[2], dim + 1)).astype(np.float32),
+                            gh_kind=(np.arange(n[2]) % 2).astype(np.uint8),
+                            anc_x=wl.uniform(rng, n[3], lo, hi),
+                            anc_p=rng.standard_normal(n[3]).astype(np.float32)))
+    pb = wl.Problem("many", dim, W, H, 0.05, np.array([1.0, 1.0, 0.7, 0.6, 0.5, 0.9]), 1e-3, subs)
+    ctx = ctx_of(pkg, pb, graph=True)
+    try:
+        L, g = gpu_loss_grad(ctx)
+        loss2, g2 = ctx.step(1, update=False, want_grad=True, per_subdomain=True)
+        torch.cuda.synchronize()
+        L2, g2 = loss2.cpu().numpy().astype(np.float64), g2.cpu().numpy().astype(np.float64)
+    finally:
+        ctx.close()
+    for k in range(300):
+        if k % 10 == 0:
+            assert np.all(L[k] == 0) and np.all(g[k] == 0) and np.all(g2[k] == 0), k
+            continue
+        Lr, gr = oracle_loss_grad(orc, pb, sub=k)
+        assert_close(g[k], gr, TOL_GRAD, f"grad sub {k}")
+        assert_close(g2[k], gr, TOL_GRAD, f"per-sub grad sub {k}")
+        nz = Lr != 0
+        assert np.all(L[k][~nz] == 0), k
+        assert_close(L[k][nz], Lr[nz], TOL_LOSS, f"loss sub {k}")
+
+
 def test_invalid_arguments_rejected(pkg):
     pb = wl.tiny(dim=2, width=5, depth=2)
     with pytest.raises(pkg.PinnError) as e:
