@@ -42,7 +42,10 @@ class SubTensors:
 def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     if t is None or t.numel() == 0:
         return None
-    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous"
+    if not (t.is_cuda and t.is_contiguous()):
+        # a host address or a strided view handed to a kernel would be read
+        # as a dense device array
+        raise ValueError("arrays passed to libddpinn must be contiguous device tensors")
     return t.data_ptr()
 
 
@@ -92,6 +95,8 @@ class Context:
         self.P = abi.num_params(dim, width, depth)
         cfg = PinnConfig()
         cfg.dim, cfg.width, cfg.depth, cfg.n_sub = dim, width, depth, self.n_sub
+        if activation not in ("tanh", "sin"):
+            raise ValueError(f"activation must be 'tanh' or 'sin', got {activation!r}")
         cfg.activation = {"tanh": 0, "sin": 1}[activation]
         self.activation = activation
         if comp_w is not None:
@@ -111,7 +116,8 @@ class Context:
         self.cfg = cfg
         arr = (PinnSubdomain * self.n_sub)()
         for i, s in enumerate(subs):
-            assert s.theta.numel() == self.P, "theta has the wrong size"
+            if s.theta.numel() != self.P:
+                raise ValueError(f"subdomain {i}: theta has {s.theta.numel()} entries, the network has {self.P}")
             d = arr[i]
             for q in range(4):
                 d.lo[q] = float(s.lo[q]) if q < len(s.lo) else 0.0
