@@ -6,9 +6,8 @@ with the reference-anchor subtraction p - p(x_anc, t) when that neighbour is a
 master, section 2.2); then all subdomains take one fused training step
 together (one grouped launch).  The targets are written into the subdomains'
 own gh_up tensors, which the step reads; between exchanges they stay fixed.
-Optional step decay of the learning rate (appendix B: factor and interval)
-is applied on the host by rebuilding nothing: the rate lives in the Adam
-kernel's arguments.
+The optional step decay of the learning rate (appendix B: factor and
+interval) is computed by pinn_step from the step number t.
 """
 from __future__ import annotations
 
