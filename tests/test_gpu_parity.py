@@ -68,8 +68,9 @@ def test_tiny_loss_grad_channels(pkg, orc, dim, W, H, npde, nobs, ngh, nanc):
     ctx.close()
 
 
-def test_config1_full_step(pkg, orc):
-    pb = wl.config1(0)
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_config1_full_step(pkg, orc, seed):
+    pb = wl.config1(seed)
     s = pb.subs[0]
     ctx = ctx_of(pkg, pb, graph=True)
     check_channels(pkg, ctx, orc, pb, s.pde_x, label="config1")
@@ -272,6 +273,37 @@ def test_many_subdomains_some_empty(pkg, orc):
         nz = Lr != 0
         assert np.all(L[k][~nz] == 0), k
         assert_close(L[k][nz], Lr[nz], TOL_LOSS, f"loss sub {k}")
+
+
+def test_failure_paths(pkg):
+    """A NaN among the collocation points makes the loss non-finite:
+    PINN_CHECK_FINITE reports PINN_E_NONFINITE (without it the step returns and
+    the loss holds the NaN).  A routed query above max_query_points is refused
+    with PINN_E_BUDGET before anything is enqueued.  Destroying a context with
+    steps in flight waits for them."""
+    pb = wl.tiny(dim=2, width=20, depth=2, n_pde=50, n_obs=5, n_gh=4, n_anc=1)
+    pb.subs[0].pde_x[17, 1] = np.nan
+    ctx = ctx_of(pkg, pb, graph=True, max_query_points=100)
+    try:
+        loss, _ = ctx.step(1, update=False)
+        torch.cuda.synchronize()
+        assert np.isnan(loss.cpu().numpy()[0, 1]) and np.isnan(loss.cpu().numpy()[0, 6])
+        with pytest.raises(pkg.PinnError) as e:
+            ctx.step(1, update=False, check_finite=True)
+        assert "NONFINITE" in str(e.value)
+        x = torch.rand(101, 3, device="cuda")
+        with pytest.raises(pkg.PinnError) as e:
+            ctx.query(x, sub=-1, what="value")
+        assert "BUDGET" in str(e.value)
+        assert ctx.query(x[:100].contiguous(), sub=-1, what="value").shape == (100, 3)
+    finally:
+        ctx.close()
+    pb = wl.tiny(dim=2, width=20, depth=2, n_pde=5000, n_obs=50, n_gh=40, n_anc=1)
+    ctx = ctx_of(pkg, pb, graph=True)
+    for t in range(1, 21):
+        ctx.step(t)
+    ctx.close()
+    torch.cuda.synchronize()
 
 
 def test_invalid_arguments_rejected(pkg):
