@@ -602,18 +602,25 @@ __device__ __forceinline__ void act_store_bwd_cols(float* buf, int S2, const v4f
   }
 }
 
-// dW_l += Zbar_l H_{l-1}^T for the rows of row block rb, into the layer's
-// block sw of the segment's slab; the old values are requested before each
-// chunk's GEMM so the read overlaps it
+// dW_l += Zbar_l H_{l-1}^T over the (row block, column block) tiles
+// [t0, t1) of the layer, row-major, into the layer's block sw of the
+// segment's slab.  A tile reads only LDS (the Zbar rows of its row block, the
+// H rows of its column block), so any wave can take any tile: the NW*NW tiles
+// are cut into equal contiguous runs, one per wave, which balances the SIMDs
+// whatever row blocks their waves own (one writer per slab float still).
+// Up to four tiles of one row block share the A operand; the old slab values
+// are requested before each group's GEMM so the read overlaps it.
 template <int NCB>
-__device__ __forceinline__ void dw_rows(float* sw, bool first, const float* bufG, int S, const float* bufH, int S2,
-                                        int NW, int rb, int g, int j, uint32_t lo16) {
-  for (int nb0 = 0; nb0 < NW; nb0 += 4) {
-    const int nnb = (NW - nb0) < 4 ? (NW - nb0) : 4;
+__device__ __forceinline__ void dw_tiles(float* sw, bool first, const float* bufG, int S, const float* bufH, int S2,
+                                         int NW, int t0, int t1, int g, int j, uint32_t lo16) {
+  for (int t = t0; t < t1;) {
+    const int rb = t / NW, nb0 = t - rb * NW;
+    int nnb = NW - nb0 < 4 ? NW - nb0 : 4;
+    if (nnb > t1 - t) nnb = t1 - t;
     v4f old[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      old[t] = (t < nnb && !first) ? ldg4u(sw + (size_t)(rb * NW + nb0 + t) * 256, lo16) : zero4();
+    for (int q = 0; q < 4; ++q)
+      old[q] = (q < nnb && !first) ? ldg4u(sw + (size_t)(rb * NW + nb0 + q) * 256, lo16) : zero4();
     v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
     switch (nnb) {
       case 4: gemm_dw<NCB, 4>(bufG, S, bufH, S2, rb, g, j, nb0, dw); break;
@@ -622,8 +629,9 @@ __device__ __forceinline__ void dw_rows(float* sw, bool first, const float* bufG
       default: gemm_dw<NCB, 1>(bufG, S, bufH, S2, rb, g, j, nb0, dw); break;
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
-      if (t < nnb) stg4u(sw + (size_t)(rb * NW + nb0 + t) * 256, lo16, old[t] + dw[t]);
+    for (int q = 0; q < 4; ++q)
+      if (q < nnb) stg4u(sw + (size_t)(rb * NW + nb0 + q) * 256, lo16, old[q] + dw[q]);
+    t += nnb;
   }
 }
 
@@ -1162,8 +1170,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
             }
             __syncthreads();
             if (raise) __builtin_amdgcn_s_setprio(2);
-            for (int r = 0; r < nrb; ++r)
-              dw_rows<NCBH>(sw, (item.flags & ITEM_FIRST) && hh == 0, bufG, S, bufH, S2, NW, w + r * NWV, g, j, lo16);
+            dw_tiles<NCBH>(sw, (item.flags & ITEM_FIRST) && hh == 0, bufG, S, bufH, S2, NW,
+                           w * NW * NW / NWV, (w + 1) * NW * NW / NWV, g, j, lo16);
             // Hbar_{l-1} of this half into the stash slot of Zbar_l (consumed)
             for (int r = 0; r < nrb; ++r) {
               const int rb = w + r * NWV;
@@ -1215,8 +1223,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           __syncthreads();
           float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
           if (raise) __builtin_amdgcn_s_setprio(2);
-          for (int r = 0; r < nrb; ++r)
-            dw_rows<NCB>(sw, item.flags & ITEM_FIRST, bufG, S, bufH, S2, NW, w + r * NWV, g, j, lo16);
+          dw_tiles<NCB>(sw, item.flags & ITEM_FIRST, bufG, S, bufH, S2, NW,
+                        w * NW * NW / NWV, (w + 1) * NW * NW / NWV, g, j, lo16);
           __builtin_amdgcn_s_setprio(0);
           // Hbar_{l-1} = W_l^T Zbar_l, then the adjoint of layer l-1, per block
           for (int r = 0; r < nrb; ++r) {
