@@ -213,6 +213,47 @@ def test_exchange_matches_oracle(pkg, orc):
     ctx.close()
 
 
+@pytest.mark.parametrize("act", ["tanh", "sin"])
+def test_exchange_3d_matches_oracle(pkg, orc, act):
+    """Two 3D subdomains side by side in x, each with a ghost slab inside the
+    other's box (a spatial face) plus a temporal ghost slab in the second;
+    the first is a master (it holds x_anc), so its sends carry the anchor
+    subtraction p - p(x_anc, t)."""
+    W, H = 24, 3
+    rng = np.random.default_rng(23)
+    boxes = [([0, 0, 0, 0], [1, 1, 1, 1]), ([1, 0, 0, 0], [2, 1, 1, 1])]
+    x_anc = [0.5, 0.5, 0.5]
+    g0 = wl.uniform(rng, 53, [1, 0, 0, 0], [1.4, 1, 1, 1])                 # sub 0's ghosts, owned by sub 1
+    g1 = np.concatenate([wl.uniform(rng, 61, [0.6, 0, 0, 0], [1, 1, 1, 1]),  # owned by sub 0
+                         wl.uniform(rng, 37, [1, 0, 0, 0.8], [2, 1, 1, 1])])  # sub 1's own later slab
+    subs = []
+    for k, ((lo, hi), gx) in enumerate(zip(boxes, (g0, g1))):
+        th = wl.xavier_theta(3, W, H, 40 + k)
+        subs.append(wl._sub(3, np.array(lo, float), np.array(hi, float), th, is_master=(k == 0),
+                            pde_x=wl.uniform(rng, 20, lo, hi), gh_x=gx,
+                            gh_up=np.zeros((len(gx), 4), np.float32), gh_kind=np.zeros(len(gx), np.uint8)))
+    pb = wl.Problem("exchange3d", 3, W, H, 0.01, np.ones(6), 1e-3, subs)
+    pb.activation = act
+    faces = [(0, 1, 0, 53), (1, 0, 0, 61)]
+    orc.set_activation(act)
+    ctx = ctx_of(pkg, pb, graph=False)
+    try:
+        targets = [torch.full((len(g0), 4), -7.0, device="cuda"), torch.full((len(g1), 4), -7.0, device="cuda")]
+        ctx.exchange(faces, x_anc, targets)
+        torch.cuda.synchronize()
+        for (a, b, first, count) in faces:
+            xg = pb.subs[a].gh_x[first:first + count]
+            ref = orc.exchange(3, W, H, pb.subs[b].theta, pb.subs[b].is_master, x_anc, xg)
+            got = targets[a][first:first + count].cpu().numpy()
+            assert_close(got[:, :3], ref[:, :3], 1e-5, f"exchange u {a}<-{b}")
+            assert_close(got[:, 3], ref[:, 3], 1e-4, f"exchange p {a}<-{b}")
+        # ghost points outside every listed face keep their values
+        assert np.all(targets[1][61:].cpu().numpy() == -7.0)
+    finally:
+        ctx.close()
+        orc.set_activation("tanh")
+
+
 def test_empty_sets_and_single_points(pkg, orc):
     pb = wl.tiny(dim=3, width=7, depth=2, n_pde=1, n_obs=0, n_gh=0, n_anc=0)
     ctx = ctx_of(pkg, pb, graph=False)
