@@ -358,3 +358,8 @@ def test_invalid_arguments_rejected(pkg):
     with pytest.raises(pkg.PinnError):
         ctx.query(torch.zeros(4, 3, device="cuda"), sub=5)
     ctx.close()
+    ctx3 = ctx_of(pkg, wl.tiny(dim=3, width=5, depth=2), graph=False)
+    with pytest.raises(pkg.PinnError) as e:      # (u, v, p, omega) is defined in 2D only
+        ctx3.query(torch.zeros(4, 4, device="cuda"), sub=0, what="uvpw")
+    assert "INVAL" in str(e.value)
+    ctx3.close()
