@@ -162,7 +162,7 @@ def cpu_baseline(pb, budget_s=12.0, one_core_s=5.0):
             "one_core": {"value": v1, "unit": "collocation pts/s", "cores": 1, "sample": s1}}
 
 
-def query_bench(seconds, seed=0, rate=200.0, budget=32 << 30):
+def query_bench(seconds, seed=0, rate=200.0, budget=32 << 30, warmup_seconds=0.0):
     import torch
 
     import workloads as wl
@@ -181,8 +181,19 @@ def query_bench(seconds, seed=0, rate=200.0, budget=32 << 30):
         reqs.append(Request(i, float(arrivals[i]), pool[o:o + n]))
         o += n
     srv = QueryServer(ctx, hbm_budget_bytes=budget, n_streams=4, max_batch_points=1 << 20)
-    # warm-up: a few requests through the same path
+    # warm-up: a few requests through the same path, then optionally an
+    # open-loop stream of the same kind for warmup_seconds (untimed)
     warm = [Request(-1 - i, 0.0, pool[:1000 * (i + 1)]) for i in range(4)]
+    if warmup_seconds > 0:
+        n_w = int(warmup_seconds * rate)
+        wa, ws = wl.query_requests(seed + 1000, n_w, rate_hz=rate)
+        ow = 0
+        for i in range(n_w):
+            m = int(ws[i])
+            if ow + m > pool.shape[0]:
+                ow = 0
+            warm.append(Request(-100 - i, float(wa[i]), pool[ow:ow + m]))
+            ow += m
     srv.run(warm)
     srv.busy_intervals.clear()
     wall = srv.run(reqs)
@@ -239,6 +250,8 @@ def main():
     ap.add_argument("--tile-points", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--query-seconds", type=float, default=8.0)
+    ap.add_argument("--query-warmup", type=float, default=0.0,
+                    help="seconds of untimed Poisson traffic before the timed query window")
     ap.add_argument("--no-query", action="store_true")
     ap.add_argument("--no-eval", action="store_true")
     ap.add_argument("--tune", action="store_true",
@@ -386,7 +399,7 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pb)
     if not args.no_query:
-        out["query"] = query_bench(args.query_seconds, seed=args.seed)
+        out["query"] = query_bench(args.query_seconds, seed=args.seed, warmup_seconds=args.query_warmup)
     if not args.no_eval:
         out["evaluate"] = eval_bench(seed=args.seed)
     print(json.dumps(out), flush=True)
