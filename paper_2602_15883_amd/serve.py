@@ -81,6 +81,13 @@ class QueryServer:
         cap = self.max_batch
         self.h_in = [torch.empty(cap, 3, dtype=torch.float32, pin_memory=True) for _ in range(n_streams)]
         self.h_out = [torch.empty(cap, 4, dtype=torch.float32, pin_memory=True) for _ in range(n_streams)]
+        # device buffers per stream slot, sized for the largest batch and
+        # allocated once: a slot is reused only after its batch has completed
+        dev = ctx.device
+        self.d_in = [torch.empty(cap, 3, dtype=torch.float32, device=dev) for _ in range(n_streams)]
+        self.d_out = [torch.empty(cap, 4, dtype=torch.float32, device=dev) for _ in range(n_streams)]
+        sb = ctx.query_scratch_bytes(cap) + 256
+        self.d_scratch = [torch.empty(sb, dtype=torch.uint8, device=dev) for _ in range(n_streams)]
         self.inflight: List[_Batch] = []
         self.inflight_bytes = 0
         self.busy_intervals = []
@@ -102,11 +109,10 @@ class QueryServer:
         with torch.cuda.stream(s):
             start_ev = torch.cuda.Event(enable_timing=True)
             start_ev.record(s)
-            x = torch.empty(n, 3, dtype=torch.float32, device=self.ctx.device)
+            x = self.d_in[slot][:n]
             x.copy_(hin[:n], non_blocking=True)
-            out = torch.empty(n, 4, dtype=torch.float32, device=self.ctx.device)
-            scratch = torch.empty(self.ctx.query_scratch_bytes(n) + 256, dtype=torch.uint8,
-                                  device=self.ctx.device)
+            out = self.d_out[slot][:n]
+            scratch = self.d_scratch[slot]
             self.ctx.query(x, sub=-1, what="uvpw", out=out, scratch=scratch, stream=s)
             hout[:n].copy_(out, non_blocking=True)
             ev = torch.cuda.Event(enable_timing=True)
@@ -136,7 +142,7 @@ class QueryServer:
         self.inflight = still
         return done
 
-    def run(self, requests: List[Request], time_scale: float = 1.0, idle_sleep: float = 2e-5):
+    def run(self, requests: List[Request], time_scale: float = 1.0, idle_sleep: float = 1e-3):
         """Serve `requests` (sorted by arrival) open loop; returns wall seconds."""
         for r in requests:
             if self.request_bytes(len(r.x)) > self.budget:
@@ -170,8 +176,14 @@ class QueryServer:
                     r.admitted = now
                 self.inflight_bytes += nbytes
                 self._launch(batch, t0)
-            if remaining and not (waiting and self.free_slots):
-                time.sleep(idle_sleep)
+            # with batches in flight, poll their events without sleeping (a
+            # sleep of a few microseconds lasts tens in practice); when idle,
+            # sleep until shortly before the next arrival (at most idle_sleep)
+            # and spin from there
+            if remaining and not self.inflight and not (waiting and self.free_slots):
+                gap = pending[0].arrival * time_scale - (time.perf_counter() - t0) if pending else 0.0
+                if gap > 3e-4:
+                    time.sleep(min(gap - 2e-4, idle_sleep))
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
