@@ -1541,6 +1541,50 @@ __global__ __launch_bounds__(kRouteBlock) void route_scatter_kernel(const RouteA
   if (s >= 0) a.perm[base[s] + rank] = (int32_t)i;
 }
 
+// A small query routed by one workgroup: subdomain of every point, counts,
+// offsets and the permutation from one launch instead of four.  Each thread
+// keeps the subdomains of its points in registers between the two passes.
+constexpr int kRouteSmallThreads = 1024;
+constexpr int kRouteSmallPerThread = 8;
+constexpr int kRouteSmallMax = kRouteSmallThreads * kRouteSmallPerThread;   // points
+
+__global__ __launch_bounds__(kRouteSmallThreads) void route_small_kernel(const RouteArgs a) {
+  extern __shared__ int sh[];   // hist[n_sub], base[n_sub]
+  int* hist = sh;
+  int* base = sh + a.n_sub;
+  for (int s = threadIdx.x; s < a.n_sub; s += blockDim.x) hist[s] = 0;
+  __syncthreads();
+  int sid[kRouteSmallPerThread];
+#pragma unroll
+  for (int k = 0; k < kRouteSmallPerThread; ++k) {
+    const int64_t i = threadIdx.x + (int64_t)k * kRouteSmallThreads;
+    sid[k] = -1;
+    if (i < a.n) {
+      const int found = route_point(a, i);
+      sid[k] = found;
+      a.sub_id[i] = found;
+      if (found >= 0) atomicAdd(&hist[found], 1);
+      else
+        for (int q = 0; q < a.out_cols; ++q) a.out[i * a.out_cols + q] = __builtin_nanf("");
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t acc = 0;
+    for (int s = 0; s < a.n_sub; ++s) {
+      base[s] = acc;
+      a.offsets[s] = acc;
+      a.counts[s] = hist[s];
+      acc += hist[s];
+    }
+    a.offsets[a.n_sub] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kRouteSmallPerThread; ++k)
+    if (sid[k] >= 0) a.perm[atomicAdd(&base[sid[k]], 1)] = (int32_t)(threadIdx.x + k * kRouteSmallThreads);
+}
+
 struct QueryLds { int S, NCOL, bufH, ys, xin, pidx, total; };
 __host__ __device__ inline QueryLds query_lds(int D, int Wp, int NCB) {
   QueryLds L;
@@ -1953,6 +1997,10 @@ hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
+  if (a.n <= kRouteSmallMax) {
+    hipLaunchKernelGGL(route_small_kernel, dim3(1), dim3(kRouteSmallThreads), 2 * sizeof(int) * (size_t)a.n_sub, s, a);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(route_zero_kernel, dim3(1), dim3(256), 0, s, a.counts, a.cursor, a.n_sub);
   const unsigned nb = (unsigned)((a.n + kRouteBlock - 1) / kRouteBlock);
   const size_t h = sizeof(int) * (size_t)a.n_sub;

@@ -177,7 +177,9 @@ def test_query_routing_and_alone_vs_mix(pkg, orc):
     pb = wl.Problem("serve", 2, 20, 3, 0.01, np.ones(6), 1e-3, subs)
     ctx = ctx_of(pkg, pb, graph=False)
     rng = np.random.default_rng(1)
-    x = wl.query_points(rng, 3001)
+    # 20,001 points: the whole batch is routed by the multi-block path, slices of
+    # up to 8,192 points by the single-workgroup path; both must agree bitwise
+    x = wl.query_points(rng, 20001)
     x[:3] = [[0, 0, 0], [8, 2, 4], [9, 1, 1]]     # corner, global upper corner, outside
     xt = torch.from_numpy(x).cuda()
     out = ctx.query(xt, sub=-1, what="uvpw").cpu().numpy()
@@ -187,7 +189,7 @@ def test_query_routing_and_alone_vs_mix(pkg, orc):
     assert_close(out[ok, :3], ref[ok, :3], 1e-5, "query uvp")
     assert_close(out[ok, 3], ref[ok, 3], 1e-4, "query vorticity")
     # each point's result is the same alone, in a small mix and in the full batch
-    for lo, hi in [(5, 6), (100, 117), (0, 3001)]:
+    for lo, hi in [(5, 6), (100, 117), (0, 3001), (3001, 3001 + 8192), (11193, 20001)]:
         part = ctx.query(xt[lo:hi].contiguous(), sub=-1, what="uvpw").cpu().numpy()
         np.testing.assert_array_equal(part, out[lo:hi])
     ctx.close()
