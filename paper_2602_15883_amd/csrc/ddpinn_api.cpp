@@ -163,6 +163,8 @@ struct pinn_ctx {
   int lds_floats = 0, qlds_floats = 0;
   int step_occ = 1;
   int query_occ[4] = {1, 1, 1, 1};   // resident query workgroups per compute unit, by query kind
+  int qlds_small_floats = 0;         // LDS of the small-tile query (value and gradient modes)
+  int query_occ_small[2] = {1, 1};   // its resident workgroups per compute unit (value, gradient)
   int exch_occ = 1;
   // grouped launch: n_wg workgroups over n_ranges item ranges (taken in
   // turn through a counter when several workgroups share a compute unit)
@@ -376,6 +378,13 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
     HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, query_kernel_ptr(sh, q), c->threads,
                                                           (size_t)c->qlds_floats * 4));
     c->query_occ[q] = std::max(1, nb);
+  }
+  c->qlds_small_floats = query_lds_floats(sh, 1);
+  for (int q = 0; q < 2; ++q) {
+    int nb = 0;
+    HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, query_kernel_ptr(sh, q, 1), c->threads,
+                                                          (size_t)c->qlds_small_floats * 4));
+    c->query_occ_small[q] = std::max(1, nb);
   }
   {
     int nb = 0;
@@ -763,8 +772,13 @@ pinn_status pinn_query(pinn_ctx* c, const float* x, int64_t n, int32_t sub, uint
   qa.nu = (float)c->cfg.nu;
   qa.lds_floats = c->qlds_floats;
   const int CF = 2 * sh.dim + 2;
-  const int npts = (what == PINN_Q_VALUE) ? 16 * CF : (what == PINN_Q_UVPW ? 16 * CF / (sh.dim + 1) : 16);
-  const int max_wg = c->num_cu * c->query_occ[what];
+  // requests too small to fill the chip take 16-point tiles: a tile's chain of
+  // layers is the latency, and smaller tiles shorten it
+  const bool small = what <= PINN_Q_UVPW && n <= 16LL * c->num_cu * c->query_occ_small[what];
+  qa.small = small ? 1 : 0;
+  if (small) qa.lds_floats = c->qlds_small_floats;
+  const int npts = small ? 16 : (what == PINN_Q_VALUE) ? 16 * CF : (what == PINN_Q_UVPW ? 16 * CF / (sh.dim + 1) : 16);
+  const int max_wg = c->num_cu * (small ? c->query_occ_small[what] : c->query_occ[what]);
   if (sub >= 0) {
     const int64_t tiles = (n + npts - 1) / npts;
     HIPCHECK(launch_query(qa, (int)std::min<int64_t>(tiles, max_wg), s));

@@ -143,7 +143,7 @@ struct QueryArgs {
   int32_t what;
   float nu;
   int32_t lds_floats;
-  int32_t pad_;
+  int32_t small;            // one 16-point block per channel (value and gradient modes)
 };
 
 struct RouteArgs {
@@ -206,7 +206,7 @@ hipError_t launch_evaluate(const EvalArgs& a, hipStream_t s);
 
 // Kernel entry points and their LDS needs (for graph nodes and occupancy).
 const void* step_kernel_ptr(const Shape& sh, int tile_points);
-const void* query_kernel_ptr(const Shape& sh, int what);   // what: Q_VALUE, Q_UVPW, Q_CHANNELS/Q_RESIDUAL
+const void* query_kernel_ptr(const Shape& sh, int what, int small = 0);   // what: Q_VALUE, Q_UVPW, Q_CHANNELS/Q_RESIDUAL
 const void* exchange_kernel_ptr(const Shape& sh);
 const void* prep_kernel_ptr();
 const void* slab_sum_kernel_ptr();
@@ -215,7 +215,7 @@ const void* clip_kernel_ptr();
 const void* adam_kernel_ptr();
 void grid_slab_sum(const ReduceArgs& a, dim3* grid, dim3* block);
 int step_lds_floats(const Shape& sh, int tile_points);
-int query_lds_floats(const Shape& sh);
+int query_lds_floats(const Shape& sh, int small = 0);
 int step_value_points(int dim, int tile_points);
 void grid_prep(const PrepArgs& a, dim3* grid, dim3* block);
 void grid_reduce(const ReduceArgs& a, dim3* grid, dim3* block);

@@ -1643,9 +1643,14 @@ __device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, f
   __syncthreads();
 }
 
-template <int DIM, int MODE, int ACT, int RPW>
+// SMALL: one 16-point block per channel of the mode instead of CF column
+// blocks, which halves (gradient mode) or divides by six (value mode) the
+// work on a tile's critical path; for requests too small to fill the chip.
+template <int DIM, int MODE, int ACT, int RPW, int SMALL>
 __global__ __launch_bounds__(512) void query_kernel(const QueryArgs a) {
-  constexpr int D = DIM + 1, CF = 2 * DIM + 2, NCB = CF;
+  constexpr int D = DIM + 1, CF = 2 * DIM + 2;
+  constexpr int CMODE = MODE == M_VALUE ? 1 : (MODE == M_GRAD ? DIM + 1 : CF);
+  constexpr int NCB = SMALL ? CMODE : CF;
   using M = ModeCfg<DIM, NCB, MODE>;
   constexpr int NPTS = M::NPTS, NCOL = 16 * NCB;
   extern __shared__ float lds[];
@@ -1926,8 +1931,8 @@ int step_lds_floats(const Shape& sh, int tile_points) {
   return sh.split ? step_lds_split(sh.D, sh.Wp, sh.H, NCB).total : step_lds(sh.D, sh.Wp, sh.H, NCB).total;
 }
 
-int query_lds_floats(const Shape& sh) {
-  return query_lds(sh.D, sh.Wp, 2 * sh.dim + 2).total;
+int query_lds_floats(const Shape& sh, int small) {
+  return query_lds(sh.D, sh.Wp, small ? sh.dim + 1 : 2 * sh.dim + 2).total;
 }
 
 // Kernel instances: dimension, tile (16 or 32 collocation points), activation,
@@ -2010,22 +2015,24 @@ hipError_t launch_route(const RouteArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int DIM, int MODE, int RPW>
+template <int DIM, int MODE, int RPW, int SMALL>
 static const void* query_ptr_act(int act) {
-  return act == ACT_SIN ? (const void*)query_kernel<DIM, MODE, ACT_SIN, RPW> : (const void*)query_kernel<DIM, MODE, ACT_TANH, RPW>;
+  return act == ACT_SIN ? (const void*)query_kernel<DIM, MODE, ACT_SIN, RPW, SMALL>
+                        : (const void*)query_kernel<DIM, MODE, ACT_TANH, RPW, SMALL>;
 }
 template <int DIM, int RPW>
-static const void* query_ptr_mode(int mode, int act) {
-  return mode == M_VALUE ? query_ptr_act<DIM, M_VALUE, RPW>(act)
-                         : (mode == M_GRAD ? query_ptr_act<DIM, M_GRAD, RPW>(act) : query_ptr_act<DIM, M_PDE, RPW>(act));
+static const void* query_ptr_mode(int mode, int act, int small) {
+  if (mode == M_VALUE) return small ? query_ptr_act<DIM, M_VALUE, RPW, 1>(act) : query_ptr_act<DIM, M_VALUE, RPW, 0>(act);
+  if (mode == M_GRAD) return small ? query_ptr_act<DIM, M_GRAD, RPW, 1>(act) : query_ptr_act<DIM, M_GRAD, RPW, 0>(act);
+  return query_ptr_act<DIM, M_PDE, RPW, 0>(act);
 }
-static const void* query_ptr(int dim, int mode, int act, int rpw) {
-  if (dim == 2) return rpw == 2 ? query_ptr_mode<2, 2>(mode, act) : query_ptr_mode<2, 1>(mode, act);
-  return rpw == 2 ? query_ptr_mode<3, 2>(mode, act) : query_ptr_mode<3, 1>(mode, act);
+static const void* query_ptr(int dim, int mode, int act, int rpw, int small) {
+  if (dim == 2) return rpw == 2 ? query_ptr_mode<2, 2>(mode, act, small) : query_ptr_mode<2, 1>(mode, act, small);
+  return rpw == 2 ? query_ptr_mode<3, 2>(mode, act, small) : query_ptr_mode<3, 1>(mode, act, small);
 }
-const void* query_kernel_ptr(const Shape& sh, int what) {
+const void* query_kernel_ptr(const Shape& sh, int what, int small) {
   const int mode = (what == Q_VALUE) ? M_VALUE : (what == Q_UVPW ? M_GRAD : M_PDE);
-  return query_ptr(sh.dim, mode, sh.act, rows_per_wave(sh));
+  return query_ptr(sh.dim, mode, sh.act, rows_per_wave(sh), small);
 }
 
 static const void* exchange_ptr(int dim, int act, int rpw) {
@@ -2043,7 +2050,7 @@ hipError_t launch_query(const QueryArgs& a, int n_wg, hipStream_t s) {
   const size_t lds = (size_t)a.lds_floats * sizeof(float);
   const dim3 block(a.sh.NWV * 64);
   void* args[] = {const_cast<QueryArgs*>(&a)};
-  return hipLaunchKernel(query_kernel_ptr(a.sh, a.what), dim3(n_wg), block, args, lds, s);
+  return hipLaunchKernel(query_kernel_ptr(a.sh, a.what, a.small), dim3(n_wg), block, args, lds, s);
 }
 
 hipError_t launch_exchange(const ExchangeArgs& a, int n_wg, hipStream_t s) {
@@ -2067,7 +2074,10 @@ hipError_t set_lds_limits(int bytes) {
       allow(step_ptr(dim, 16, act, 2, 0));
       allow(step_ptr(dim, 16, act, 2, 1));
       for (int rpw = 1; rpw <= 2; ++rpw) {
-        for (int mode : {M_PDE, M_VALUE, M_GRAD}) allow(query_ptr(dim, mode, act, rpw));
+        for (int mode : {M_PDE, M_VALUE, M_GRAD}) {
+          allow(query_ptr(dim, mode, act, rpw, 0));
+          allow(query_ptr(dim, mode, act, rpw, 1));
+        }
         allow(exchange_ptr(dim, act, rpw));
       }
     }

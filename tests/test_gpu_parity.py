@@ -195,6 +195,35 @@ def test_query_routing_and_alone_vs_mix(pkg, orc):
     ctx.close()
 
 
+def test_small_and_regular_query_tiles_agree(pkg, orc):
+    """A request too small to fill the chip runs 16-point tiles; larger ones run
+    the regular tiles.  Every column is computed the same way in both, so a
+    point's result is bitwise the same whichever tile it lands in; both agree
+    with the oracle."""
+    W, H = 100, 2
+    boxes, thetas = wl.serving_nets(seed=7, width=W, depth=H)
+    subs = [wl._sub(2, boxes[s][0], boxes[s][1], thetas[s]) for s in range(len(thetas))]
+    pb = wl.Problem("serve_tiles", 2, W, H, 0.01, np.ones(6), 1e-3, subs)
+    ctx = ctx_of(pkg, pb, graph=False)
+    try:
+        x = torch.from_numpy(wl.query_points(np.random.default_rng(4), 50_000)).cuda()
+        for what in ("uvpw", "value"):
+            full = ctx.query(x, sub=-1, what=what).cpu().numpy()
+            for lo in range(0, 50_000, 12_000):
+                part = ctx.query(x[lo:lo + 2000].contiguous(), sub=-1, what=what).cpu().numpy()
+                np.testing.assert_array_equal(part, full[lo:lo + 2000])
+            if what == "uvpw":
+                ref = orc.query2d(W, H, thetas, boxes, x[:3000].cpu().numpy())
+                ok = ~np.isnan(ref[:, 0])
+                assert_close(full[:3000][ok, :3], ref[ok, :3], 1e-5, "uvp")
+        # single-subdomain queries take the same two paths
+        y = x[:40_000].contiguous()
+        one = ctx.query(y, sub=3, what="value").cpu().numpy()
+        np.testing.assert_array_equal(ctx.query(y[:1000].contiguous(), sub=3, what="value").cpu().numpy(), one[:1000])
+    finally:
+        ctx.close()
+
+
 def test_exchange_matches_oracle(pkg, orc):
     pb = wl.config3(0, pde_range=(100, 200), n_obs=10, n_gh_face=50)
     ctx = ctx_of(pkg, pb, graph=False)
