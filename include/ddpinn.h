@@ -67,9 +67,11 @@ typedef enum {
 #define PINN_PER_SUBDOMAIN 4u  /* one plain launch of the fused kernel per
                                   subdomain instead of the grouped launch
                                   (same results; for comparison)             */
-#define PINN_TIME_KERNEL 8u    /* run the step without the graph and record
-                                  HIP events on `stream` around the fused
-                                  kernel launch(es); see pinn_kernel_time     */
+#define PINN_TIME_KERNEL 8u    /* run the step without the graph, launching
+                                  the fused kernel with HIP events tied to
+                                  the dispatch (its start and end time
+                                  stamps, kernel execution only); see
+                                  pinn_kernel_time                            */
 
 /* pinn_query `what` */
 #define PINN_Q_VALUE 0u        /* out[n][d+1]   = (u_1..u_d, p)                */
@@ -92,7 +94,9 @@ typedef struct {
   double nu;              /* kinematic viscosity 1/Re                         */
   float lam[6];           /* obs, PDE, gh_u, gh_p^space, gh_p^time, anchor    */
   float lr, beta1, beta2, eps;   /* Adam                                      */
-  int32_t tile_points;    /* collocation points per tile: 0 = tuned, 16, 32   */
+  int32_t tile_points;    /* collocation points per tile: 16 or 32; 0 means
+                             16.  The shapes measured fastest per network
+                             are in the package's tuning table (tune.py)   */
   int32_t blocks_per_cu;  /* persistent workgroups per CU: 0 = occupancy max  */
   int64_t max_query_points; /* largest n accepted by pinn_query (routing)     */
   float comp_w[3];        /* weights of the velocity components in L_obs and
@@ -178,6 +182,13 @@ pinn_status pinn_query(pinn_ctx *ctx, const float *x, int64_t n, int32_t sub,
  * targets[a] (same layout as gh_up; may alias the gh_up the context reads).
  * faces: host array of n_faces records {a, b, first, count}.
  * x_anc: host [d] anchor location.
+ * Stream-ordered and never synchronizing: each exchange runs on the device
+ * after the previous exchange of the context (whatever its stream); a
+ * changed face list or targets array is uploaded from a host copy the
+ * library keeps until that upload has run, so the caller's arrays may be
+ * reused as soon as the call returns.  PINN_E_NOMEM if the faces need more
+ * work tiles than the workspace holds (sized at create for every ghost
+ * point).
  */
 typedef struct { int32_t a, b; int64_t first, count; } pinn_face;
 pinn_status pinn_exchange(pinn_ctx *ctx, const pinn_face *faces, int32_t n_faces,
@@ -187,7 +198,8 @@ pinn_status pinn_exchange(pinn_ctx *ctx, const pinn_face *faces, int32_t n_faces
  * Durations of the fused-kernel launches recorded by PINN_TIME_KERNEL steps
  * since the previous call: waits for them, writes their sum in milliseconds
  * and their number, and forgets them.  With PINN_PER_SUBDOMAIN one recorded
- * launch spans all per-subdomain launches of the step.
+ * launch spans all per-subdomain launches of the step, from the start of the
+ * first to the end of the last.
  */
 pinn_status pinn_kernel_time(pinn_ctx *ctx, double *total_ms, int64_t *launches);
 

@@ -198,7 +198,16 @@ struct pinn_ctx {
   int x_cap = 0;
   std::vector<ExchangeItem> x_host;
   std::vector<float*> x_targets_host;
-  bool x_pending = false;
+  // exchange: each launch is ordered after the previous one (x_done), on
+  // whatever stream; host copies of a changed work list stay alive until the
+  // copy that reads them has run (x_staged, reaped without waiting)
+  hipEvent_t x_done = nullptr;
+  bool x_done_recorded = false;
+  struct Staged {
+    std::vector<char> bytes;
+    hipEvent_t copied;
+  };
+  std::vector<Staged*> x_staged;
   float gmax[4] = {0, 0, 0, 0};
   // graph
   hipGraph_t graph = nullptr;
@@ -670,16 +679,34 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
 static pinn_status run_step_eager(pinn_ctx* c, bool per_sub, bool timed, hipStream_t s) {
   HIPCHECK(launch_prep(c->pargs, s));
   ReduceArgs ra = c->rargs;
+  // timed launches: the events are tied to the dispatches themselves (start
+  // time stamp of the first step-kernel launch, end time stamp of the last),
+  // so the measured span holds kernel execution only
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed) {
     pinn_status st = next_event_pair(c, &e0, &e1);
     if (st != PINN_OK) return st;
-    HIPCHECK(hipEventRecord(e0, s));
   }
   if (!per_sub) {
-    if (c->n_items) HIPCHECK(launch_step(c->sargs, c->tile_points, c->n_wg, s));
+    if (c->n_items) {
+      if (timed) HIPCHECK(launch_step_timed(c->sargs, c->tile_points, c->n_wg, s, e0, e1));
+      else HIPCHECK(launch_step(c->sargs, c->tile_points, c->n_wg, s));
+    } else if (timed) {
+      HIPCHECK(hipEventRecord(e0, s));
+      HIPCHECK(hipEventRecord(e1, s));
+    }
   } else {
     // one plain launch per subdomain over its own partition and slabs
+    int first = -1, last = -1;
+    for (int k = 0; k < c->n_sub; ++k)
+      if (c->ps_wg[k]) {
+        if (first < 0) first = k;
+        last = k;
+      }
+    if (timed && first < 0) {
+      HIPCHECK(hipEventRecord(e0, s));
+      HIPCHECK(hipEventRecord(e1, s));
+    }
     for (int k = 0; k < c->n_sub; ++k) {
       if (!c->ps_wg[k]) continue;
       StepArgs a = c->sargs;
@@ -687,11 +714,12 @@ static pinn_status run_step_eager(pinn_ctx* c, bool per_sub, bool timed, hipStre
       a.wg_begin = c->d_wgb_ps + c->ps_wgb_off[k];
       a.counter = c->dynamic ? c->d_counters + 1 + k : nullptr;
       a.n_ranges = c->ps_nr[k];
-      HIPCHECK(launch_step(a, c->tile_points, c->ps_wg[k], s));
+      if (timed) HIPCHECK(launch_step_timed(a, c->tile_points, c->ps_wg[k], s, k == first ? e0 : nullptr,
+                                            k == last ? e1 : nullptr));
+      else HIPCHECK(launch_step(a, c->tile_points, c->ps_wg[k], s));
     }
     ra.seg_begin = c->d_seg_ps;
   }
-  if (timed) HIPCHECK(hipEventRecord(e1, s));
   HIPCHECK(launch_reduce(ra, s));
   HIPCHECK(launch_prep(c->pargs, s));
   return PINN_OK;
@@ -840,17 +868,43 @@ pinn_status pinn_exchange(pinn_ctx* c, const pinn_face* faces, int32_t n_faces, 
   if ((int)its.size() > c->x_cap) return fail(PINN_E_NOMEM, "exchange needs %zu tiles > capacity %d", its.size(), c->x_cap);
   if (its.empty()) return PINN_OK;
   hipStream_t s = (hipStream_t)stream;
+  if (!c->x_done) HIPCHECK(hipEventCreateWithFlags(&c->x_done, hipEventDisableTiming));
+  // stream order only, never a host wait: this exchange (its copies of the
+  // work list and its launch) runs after the previous exchange, whichever
+  // stream that was on, so the device work list is not rewritten under it
+  if (c->x_done_recorded) HIPCHECK(hipStreamWaitEvent(s, c->x_done, 0));
+  // host copies whose upload has run are released (queried, not waited for)
+  for (size_t k = 0; k < c->x_staged.size();) {
+    if (hipEventQuery(c->x_staged[k]->copied) == hipSuccess) {
+      (void)hipEventDestroy(c->x_staged[k]->copied);
+      delete c->x_staged[k];
+      c->x_staged[k] = c->x_staged.back();
+      c->x_staged.pop_back();
+    } else {
+      ++k;
+    }
+  }
   std::vector<float*> tg(targets, targets + c->n_sub);
   const bool same = its.size() == c->x_host.size() &&
                     std::memcmp(its.data(), c->x_host.data(), its.size() * sizeof(ExchangeItem)) == 0 &&
                     tg == c->x_targets_host;
   if (!same) {
-    if (c->x_pending) HIPCHECK(hipDeviceSynchronize());
     c->x_host = its;
     c->x_targets_host = tg;
-    HIPCHECK(hipMemcpyAsync(c->d_xitems, c->x_host.data(), sizeof(ExchangeItem) * its.size(), hipMemcpyHostToDevice, s));
-    HIPCHECK(hipMemcpyAsync(c->d_targets, c->x_targets_host.data(), sizeof(float*) * c->n_sub, hipMemcpyHostToDevice, s));
-    c->x_pending = true;
+    // the upload reads a host copy that lives until the copy has run
+    const size_t ib = sizeof(ExchangeItem) * its.size(), tb = sizeof(float*) * c->n_sub;
+    auto* st = new pinn_ctx::Staged{std::vector<char>(ib + tb), nullptr};
+    std::memcpy(st->bytes.data(), its.data(), ib);
+    std::memcpy(st->bytes.data() + ib, tg.data(), tb);
+    hipError_t e = hipEventCreateWithFlags(&st->copied, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete st;
+      return fail(PINN_E_DEVICE, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    c->x_staged.push_back(st);
+    HIPCHECK(hipMemcpyAsync(c->d_xitems, st->bytes.data(), ib, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(c->d_targets, st->bytes.data() + ib, tb, hipMemcpyHostToDevice, s));
+    HIPCHECK(hipEventRecord(st->copied, s));
   }
   ExchangeArgs ea{};
   ea.sh = sh;
@@ -861,6 +915,8 @@ pinn_status pinn_exchange(pinn_ctx* c, const pinn_face* faces, int32_t n_faces, 
   ea.targets = c->d_targets;
   for (int q = 0; q < sh.dim; ++q) ea.x_anc[q] = x_anc[q];
   HIPCHECK(launch_exchange(ea, (int)std::min<int64_t>((int64_t)its.size(), (int64_t)c->num_cu * c->exch_occ), s));
+  HIPCHECK(hipEventRecord(c->x_done, s));
+  c->x_done_recorded = true;
   return PINN_OK;
 }
 
@@ -1002,6 +1058,11 @@ pinn_status pinn_destroy(pinn_ctx* c) {
   g_err.clear();
   if (!c) return PINN_OK;
   hipError_t e = hipDeviceSynchronize();
+  for (pinn_ctx::Staged* st : c->x_staged) {
+    (void)hipEventDestroy(st->copied);
+    delete st;
+  }
+  if (c->x_done) (void)hipEventDestroy(c->x_done);
   for (hipEvent_t ev : c->ev_start) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : c->ev_stop) (void)hipEventDestroy(ev);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);

@@ -196,6 +196,8 @@ struct EvalArgs {
 // Launchers (ddpinn_kernels.hip)
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int tile_points, int n_wg, hipStream_t s);
+hipError_t launch_step_timed(const StepArgs& a, int tile_points, int n_wg, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 hipError_t launch_route(const RouteArgs& a, hipStream_t s);
 hipError_t launch_query(const QueryArgs& a, int n_wg, hipStream_t s);

@@ -1990,6 +1990,18 @@ hipError_t launch_step(const StepArgs& a, int tile_points, int n_wg, hipStream_t
   return hipLaunchKernel(k, dim3(n_wg), block, args, lds, s);
 }
 
+// the same launch with events tied to the dispatch itself: e0 takes the
+// kernel's start and e1 its end time stamp (either may be null)
+hipError_t launch_step_timed(const StepArgs& a, int tile_points, int n_wg, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
+  const size_t lds = (size_t)a.lds_floats * sizeof(float);
+  const void* k = step_kernel_ptr(a.sh, tile_points);
+  if (!k) return hipErrorInvalidValue;
+  const dim3 block(a.sh.NWV * 64);
+  void* args[] = {const_cast<StepArgs*>(&a)};
+  return hipExtLaunchKernel(k, dim3(n_wg), block, args, lds, s, e0, e1, 0);
+}
+
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
   dim3 grid, block;
   grid_slab_sum(a, &grid, &block);

@@ -9,6 +9,13 @@ issues each batch on one of several HIP streams: host-to-device copy, routed
 query (pinn_query), device-to-host copy, completion event.  Per-point results
 do not depend on the batch a point lands in, so a request's result is the same
 alone and in the mix.
+
+Device memory: the server allocates one arena at construction and never
+again.  The arena holds one batch slot per stream (input points, outputs and
+routing scratch for max_batch_points points); the number of slots is the
+number of streams, reduced until the arena fits the HBM budget.  A batch
+occupies a slot until its completion event has fired, so the memory the
+requests in flight use is bounded by the budget, not just counted against it.
 """
 from __future__ import annotations
 
@@ -22,7 +29,8 @@ import torch
 
 from .context import Context, SubTensors
 
-BYTES_PER_POINT = 3 * 4 + 4 * 4 + 2 * 4   # points in, (u, v, p, w) out, routing scratch
+def _align(n: int) -> int:
+    return (int(n) + 255) & ~255
 
 
 def serving_context(boxes, thetas, width: int, depth: int, dim: int = 2, nu: float = 0.01,
@@ -55,6 +63,7 @@ class Request:
     out: Optional[np.ndarray] = None
     done: float = -1.0             # completion visible on host (s)
     admitted: float = -1.0
+    deferred: bool = False         # waited for a free batch slot
 
 
 @dataclass
@@ -76,25 +85,45 @@ class QueryServer:
         self.ctx = ctx
         self.budget = int(hbm_budget_bytes)
         self.max_batch = int(max_batch_points)
-        self.streams = [torch.cuda.Stream(device=ctx.device) for _ in range(n_streams)]
-        self.free_slots = deque(range(n_streams))
         cap = self.max_batch
-        self.h_in = [torch.empty(cap, 3, dtype=torch.float32, pin_memory=True) for _ in range(n_streams)]
-        self.h_out = [torch.empty(cap, 4, dtype=torch.float32, pin_memory=True) for _ in range(n_streams)]
-        # device buffers per stream slot, sized for the largest batch and
-        # allocated once: a slot is reused only after its batch has completed
-        dev = ctx.device
-        self.d_in = [torch.empty(cap, 3, dtype=torch.float32, device=dev) for _ in range(n_streams)]
-        self.d_out = [torch.empty(cap, 4, dtype=torch.float32, device=dev) for _ in range(n_streams)]
-        sb = ctx.query_scratch_bytes(cap) + 256
-        self.d_scratch = [torch.empty(sb, dtype=torch.uint8, device=dev) for _ in range(n_streams)]
+        # one batch slot: points in, outputs, routing scratch (256-byte aligned parts)
+        self.in_bytes = _align(cap * 3 * 4)
+        self.out_bytes = _align(cap * 4 * 4)
+        self.scratch_bytes = _align(ctx.query_scratch_bytes(cap))
+        self.slot_bytes = self.in_bytes + self.out_bytes + self.scratch_bytes
+        n_slots = min(int(n_streams), self.budget // self.slot_bytes)
+        if n_slots < 1:
+            raise ValueError(f"an HBM budget of {self.budget} bytes holds no batch slot of "
+                             f"{cap} points ({self.slot_bytes} bytes); lower max_batch_points")
+        self.n_slots = n_slots
+        self.streams = [torch.cuda.Stream(device=ctx.device) for _ in range(n_slots)]
+        self.free_slots = deque(range(n_slots))
+        self.h_in = [torch.empty(cap, 3, dtype=torch.float32, pin_memory=True) for _ in range(n_slots)]
+        self.h_out = [torch.empty(cap, 4, dtype=torch.float32, pin_memory=True) for _ in range(n_slots)]
+        # the only device allocation of the server: n_slots slots in one arena
+        self.arena = torch.empty(n_slots * self.slot_bytes, dtype=torch.uint8, device=ctx.device)
+        self.d_in, self.d_out, self.d_scratch = [], [], []
+        for k in range(n_slots):
+            base = k * self.slot_bytes
+            seg = self.arena[base:base + self.slot_bytes]
+            self.d_in.append(seg[:cap * 12].view(torch.float32).view(cap, 3))
+            o = self.in_bytes
+            self.d_out.append(seg[o:o + cap * 16].view(torch.float32).view(cap, 4))
+            o += self.out_bytes
+            self.d_scratch.append(seg[o:o + self.scratch_bytes])
         self.inflight: List[_Batch] = []
         self.inflight_bytes = 0
         self.busy_intervals = []
         self.deferred = 0
 
+    @property
+    def device_bytes(self) -> int:
+        """Device memory the server holds (the arena)."""
+        return self.arena.numel()
+
     def request_bytes(self, n: int) -> int:
-        return n * BYTES_PER_POINT + self.ctx.query_scratch_bytes(0) + 4096
+        """Device bytes a request of n points uses inside its batch slot."""
+        return _align(n * 12) + _align(n * 16) + _align(self.ctx.query_scratch_bytes(n))
 
     # -------------------------------------------------------------- dispatch
     def _launch(self, reqs: List[Request], t0: float):
@@ -145,10 +174,9 @@ class QueryServer:
     def run(self, requests: List[Request], time_scale: float = 1.0, idle_sleep: float = 1e-3):
         """Serve `requests` (sorted by arrival) open loop; returns wall seconds."""
         for r in requests:
-            if self.request_bytes(len(r.x)) > self.budget:
-                raise ValueError(f"request {r.rid} of {len(r.x)} points exceeds the HBM budget")
             if len(r.x) > self.max_batch:
-                raise ValueError(f"request {r.rid} exceeds max_batch_points")
+                raise ValueError(f"request {r.rid} of {len(r.x)} points exceeds a batch slot "
+                                 f"({self.max_batch} points) of the HBM budget")
         pending = deque(requests)
         waiting: deque = deque()
         remaining = len(requests)
@@ -158,24 +186,31 @@ class QueryServer:
             while pending and pending[0].arrival * time_scale <= now:
                 waiting.append(pending.popleft())
             remaining -= self._poll(t0)
-            # admission: whole requests, oldest first, while memory and a stream are free
+            # admission: whole requests, oldest first, while a batch slot (its
+            # share of the HBM budget) is free; a request that does not fit the
+            # slot being filled waits for the next one
             while waiting and self.free_slots:
                 batch, n, nbytes = [], 0, 0
                 while waiting:
                     r = waiting[0]
                     rb = self.request_bytes(len(r.x))
-                    if n + len(r.x) > self.max_batch or self.inflight_bytes + nbytes + rb > self.budget:
+                    if n + len(r.x) > self.max_batch:
                         break
                     batch.append(waiting.popleft())
                     n += len(r.x)
                     nbytes += rb
                 if not batch:
-                    self.deferred += 1
                     break
                 for r in batch:
                     r.admitted = now
                 self.inflight_bytes += nbytes
                 self._launch(batch, t0)
+            # requests still waiting had no free batch slot: count each once
+            for r in reversed(waiting):
+                if r.deferred:
+                    break
+                r.deferred = True
+                self.deferred += 1
             # with batches in flight, poll their events without sleeping (a
             # sleep of a few microseconds lasts tens in practice); when idle,
             # sleep until shortly before the next arrival (at most idle_sleep)

@@ -20,7 +20,11 @@ from typing import Dict, List, Optional
 
 import torch
 
+from .abi import PINN_E_INVAL, PINN_E_UNSUPPORTED, PinnError
 from .context import Context
+
+# statuses of a launch shape the library refuses before enqueueing any work
+REJECTED = (PINN_E_INVAL, PINN_E_UNSUPPORTED)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SHIPPED = os.path.join(HERE, "tuned.json")
@@ -124,12 +128,18 @@ def autotune(make_ctx, dim, width, depth, n_sub, n_pde, steps: int = 3,
     cands = candidates(width)
     try:   # one untimed pass first: the first launch of a process pays start-up costs
         measure(make_ctx, cands[0], steps=1)
-    except Exception:
-        pass
+    except PinnError as ex:
+        if ex.status not in REJECTED:
+            raise
     for cand in cands:
         try:
             ms = measure(make_ctx, cand, steps=steps, seen=seen)
-        except Exception as ex:  # a candidate the library rejects
+        except PinnError as ex:
+            # only a candidate the library rejects before launching anything is
+            # skipped; any other failure (a device error) ends the tuning run
+            # without storing a result
+            if ex.status not in REJECTED:
+                raise
             if verbose:
                 print("tune: skip", cand, ex)
             continue

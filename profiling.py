@@ -3,9 +3,13 @@ HBM traffic scaled by a copy-kernel calibration).
 
 Usage (on the host that holds the rocprofv3 output directories):
 
-  python -m paper_2602_15883_amd.profiling stats  TRACE_DIR  OUT.md  "command"
-  python -m paper_2602_15883_amd.profiling counters OUT.md "command" DIR...
-  python -m paper_2602_15883_amd.profiling traffic WORKLOAD FETCH_DIR WRITE_DIR COPY_BYTES
+  python profiling.py stats  TRACE_DIR  OUT.md  "command"
+  python profiling.py counters OUT.md "command" DIR...
+  python profiling.py traffic WORKLOAD FETCH_DIR WRITE_DIR COPY_BYTES
+
+`stats` also lists, from the per-dispatch trace, each kernel's median
+duration and its mean over the launches after the first few (the first
+launches of a run are slower: cold caches and clocks).
 
 `traffic` scales each counter by (bytes the calibration copy really moved) /
 (what the same counter reported for it), and records the result with the
@@ -21,8 +25,8 @@ import os
 import sys
 from collections import defaultdict
 
-HERE = os.path.dirname(os.path.abspath(__file__))
-ROOT = os.path.dirname(HERE)
+ROOT = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_2602_15883_amd", "csrc")
 STEP_KERNEL = "step_kernel"
 COPY_KERNEL = "neg_kernel"
 
@@ -34,7 +38,7 @@ def _csvs(d, suffix):
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("ddpinn_kernels.hip", "ddpinn_internal.h"):
-        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+        with open(os.path.join(CSRC, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -50,6 +54,20 @@ def stats(trace_dir: str):
             for r in csv.DictReader(f):
                 rows.append(r)
     return rows
+
+
+def dispatch_durations(trace_dir: str):
+    """{kernel name: [duration ns of each dispatch, in dispatch order]}"""
+    out = defaultdict(list)
+    for path in _csvs(trace_dir, "kernel_trace.csv"):
+        rows = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                rows.append((int(r["Start_Timestamp"]), r["Kernel_Name"],
+                             int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        for _t, name, d in sorted(rows):
+            out[name].append(d)
+    return out
 
 
 def counter_values(d: str):
@@ -69,14 +87,23 @@ def _find(kv, sub):
     return None
 
 
-def write_stats_md(trace_dir, out_md, command):
+def write_stats_md(trace_dir, out_md, command, skip_first=3):
     rows = stats(trace_dir)
+    durs = dispatch_durations(trace_dir)
     lines = [f"# Kernel time: {os.path.basename(out_md)[:-3]}", "",
              "Command (rocprofv3, run from /tmp on the GPU host):", "", "```", command, "```", "",
-             "| Kernel | Calls | Average (us) | Min (us) | Max (us) | Share (%) |",
-             "|---|---|---|---|---|---|"]
+             f"Median and 'mean after {skip_first}' (the mean over the dispatches after the first "
+             f"{skip_first} of each kernel) come from the per-dispatch kernel trace.", "",
+             "| Kernel | Calls | Average (us) | Median (us) | Mean after " + str(skip_first) +
+             " (us) | Min (us) | Max (us) | Share (%) |",
+             "|---|---|---|---|---|---|---|---|"]
     for r in rows:
+        d = sorted(durs.get(r["Name"], []))
+        tail = durs.get(r["Name"], [])[skip_first:]
+        med = f"{d[len(d) // 2] / 1e3:.1f}" if d else "-"
+        mt = f"{sum(tail) / len(tail) / 1e3:.1f}" if tail else "-"
         lines.append(f"| `{short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                     f"{med} | {mt} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.2f} |")
     with open(out_md, "w") as f:

@@ -110,3 +110,74 @@ def test_cylinder3d_paper_full_size_halves(pkg):
     600,000 + 100,000 points."""
     _halves(pkg, wl.cylinder3d_paper(0), "cylinder3d_paper")
 
+
+
+@pytest.mark.parametrize("name,n_pde,n_obs", [("cylinder3d_paper", 16_384, 2_048),
+                                              ("cylinder2d_paper", 16_384, 2_048)])
+def test_paper_cylinder_network_vs_oracle(pkg, orc, name, n_pde, n_obs):
+    """The paper's cylinder networks at the shape they run at (3D: sine 8x200,
+    column-split LDS plan; 2D: sine 6x150, two row blocks per wave) on the
+    first 16,384 collocation and 2,048 observation points of their workloads,
+    in the benchmark's launch configuration (graph, library launch shape):
+    about four collocation tiles per workgroup, so the slab accumulation over
+    several tiles runs; the whole loss and gradient against the oracle."""
+    full = getattr(wl, name)(0)
+    s = full.subs[0]
+    sub = dataclasses.replace(s, pde_x=np.ascontiguousarray(s.pde_x[:n_pde]),
+                              obs_x=np.ascontiguousarray(s.obs_x[:n_obs]),
+                              obs_u=np.ascontiguousarray(s.obs_u[:n_obs]))
+    pb = dataclasses.replace(full, subs=[sub])
+    print(f"{name}: {n_pde} collocation + {n_obs} observation points", flush=True)
+    orc.set_activation(pb.activation)
+    orc.set_component_weights(pb.comp_w)
+    try:
+        ctx = pkg.context_from_problem(pb, device="cuda", graph=True)
+        try:
+            info = ctx.launch_info()
+            assert info["n_items"] >= 3 * info["n_wg"]     # several tiles per workgroup
+            loss, g = ctx.step(1, update=False, want_grad=True)
+            torch.cuda.synchronize()
+            L = loss.cpu().numpy()[0].astype(np.float64)
+            G = g.cpu().numpy()[0].astype(np.float64)
+        finally:
+            ctx.close()
+        Lr, gr = oracle_loss_grad(orc, pb)
+        assert_close(L, Lr, TOL_LOSS, f"{name} loss")
+        assert_close(G, gr, TOL_GRAD, f"{name} grad")
+    finally:
+        orc.set_activation("tanh")
+        orc.set_component_weights(None)
+
+
+def test_serving_networks_routed_query_vs_oracle(pkg, orc):
+    """The serving workload's networks (16 resident 3->8x100->3 experts on the
+    [0,8] x [0,2] x [0,4] strips and slabs): routed (u, v, p, v_x - u_y) on
+    24,000 points, among them points on every interior face (half-open
+    ownership), on the outer faces and at the global upper corner, against
+    the oracle's stitched query."""
+    from paper_2602_15883_amd.serve import serving_context
+    boxes, thetas = wl.serving_nets(0, width=100, depth=8)
+    ctx = serving_context(boxes, thetas, 100, 8, device="cuda")
+    rng = np.random.default_rng(31)
+    x = wl.query_points(rng, 24_000)
+    k = 0
+    for xf in (0.0, 2.0, 4.0, 6.0, 8.0):          # strip faces, outer faces included
+        x[k:k + 200, 0] = xf
+        k += 200
+    for tf in (0.0, 1.0, 2.0, 3.0, 4.0):          # slab faces
+        x[k:k + 200, 2] = tf
+        k += 200
+    for yf in (0.0, 2.0):
+        x[k:k + 200, 1] = yf
+        k += 200
+    x[k] = [8.0, 2.0, 4.0]                        # the global upper corner
+    x[k + 1] = [2.0, 1.0, 1.0]                    # on an edge of four boxes
+    x[k + 2] = [0.0, 0.0, 0.0]
+    try:
+        out = ctx.query(torch.from_numpy(x).cuda(), sub=-1, what="uvpw").cpu().numpy()
+    finally:
+        ctx.close()
+    ref = orc.query2d(100, 8, thetas, boxes, x)
+    assert not np.any(np.isnan(ref)) and not np.any(np.isnan(out))
+    assert_close(out[:, :3], ref[:, :3], 1e-5, "query uvp")
+    assert_close(out[:, 3], ref[:, 3], 1e-4, "query vorticity")

@@ -46,16 +46,45 @@ def test_results_same_alone_and_in_mix(server_parts, orc):
 def test_small_budget_defers_without_error(server_parts):
     serve, ctx, _, _ = server_parts
     reqs = make_requests(serve, 40, seed=5, nmax=20000, rate=1e6)   # all arrive at once
-    budget = 2 * serve.QueryServer(ctx).request_bytes(20000)
+    one = serve.QueryServer(ctx, n_streams=1, max_batch_points=20000)
+    budget = 2 * one.slot_bytes
+    del one
     srv = serve.QueryServer(ctx, hbm_budget_bytes=budget, n_streams=4, max_batch_points=20000)
+    assert srv.n_slots == 2 and srv.device_bytes <= budget
     srv.run(reqs)
     assert srv.deferred > 0
     assert all(r.out is not None and r.out.shape == (len(r.x), 4) for r in reqs)
 
 
+def test_16mb_budget_bounds_device_memory(server_parts):
+    """Admission at a 16 MB HBM budget: the server's own device allocation
+    stays within the budget while requests of up to 200,000 points are
+    served (they wait for a free batch slot)."""
+    serve, ctx, _, _ = server_parts
+    budget = 16 << 20
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    srv = serve.QueryServer(ctx, hbm_budget_bytes=budget, n_streams=4, max_batch_points=200_000)
+    held = torch.cuda.memory_allocated() - before
+    assert held <= budget and srv.device_bytes <= budget
+    assert 1 <= srv.n_slots < 4
+    arr, sizes = wl.query_requests(8, 12, rate_hz=1e5, nmax=200_000)
+    sizes[:3] = [200_000, 150_000, 1]
+    rng = np.random.default_rng(8)
+    reqs = [serve.Request(i, float(arr[i]), wl.query_points(rng, int(sizes[i]))) for i in range(12)]
+    srv.run(reqs)
+    assert torch.cuda.memory_allocated() - before <= budget
+    assert srv.deferred > 0
+    for r in reqs[:3]:
+        alone = ctx.query(torch.from_numpy(r.x).cuda(), sub=-1, what="uvpw").cpu().numpy()
+        np.testing.assert_array_equal(r.out, alone)
+
+
 def test_request_over_budget_is_rejected(server_parts):
     serve, ctx, _, _ = server_parts
-    srv = serve.QueryServer(ctx, hbm_budget_bytes=1 << 16, n_streams=1, max_batch_points=1 << 16)
+    with pytest.raises(ValueError):   # not even one batch slot fits the budget
+        serve.QueryServer(ctx, hbm_budget_bytes=1 << 16, n_streams=1, max_batch_points=1 << 16)
+    srv = serve.QueryServer(ctx, hbm_budget_bytes=1 << 24, n_streams=1, max_batch_points=1 << 14)
     big = serve.Request(0, 0.0, np.zeros((50000, 3), np.float32))
-    with pytest.raises(ValueError):
+    with pytest.raises(ValueError):   # larger than a batch slot
         srv.run([big])
