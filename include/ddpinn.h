@@ -175,6 +175,22 @@ pinn_status pinn_query(pinn_ctx *ctx, const float *x, int64_t n, int32_t sub,
                        void *stream);
 
 /*
+ * pinn_query without the scratch argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  Same arguments and results as pinn_query (the same
+ * kernels), but a routed query (sub == -1) uses a routing scratch the library
+ * holds in a fixed device array of about 8.4 MB per GPU (kept until the
+ * process ends), so n is limited to 1,048,576 routed points: PINN_E_BUDGET
+ * beyond that (and beyond cfg.max_query_points), before anything is enqueued.
+ * Calls no allocating routine.  Every call on one GPU shares that GPU's
+ * array, whose contents persist between calls (the kernels write every part
+ * they read before reading it): calls that may overlap on one GPU, from any
+ * context or stream, race on it and must be ordered by the caller.
+ */
+pinn_status pinn_query_noalloc(pinn_ctx *ctx, const float *x, int64_t n, int32_t sub,
+                               uint32_t what, float *out, void *stream);
+
+/*
  * Ghost-target exchange (section 2.2 reference anchor normalisation,
  * Algorithm 1 exchange branch): for every subdomain a and every ghost point
  * of a listed in `faces`, write gh_up of a = (u_b, p_b - [b master] p_b(x_anc, t))

@@ -31,7 +31,7 @@ PINN_Q_RESIDUAL = 3
 
 # every symbol include/ddpinn.h declares
 EXPORTS = ("pinn_num_params", "pinn_create", "pinn_step", "pinn_query_scratch_bytes",
-           "pinn_query", "pinn_exchange", "pinn_refresh", "pinn_destroy",
+           "pinn_query", "pinn_query_noalloc", "pinn_exchange", "pinn_refresh", "pinn_destroy",
            "pinn_get_launch_info", "pinn_last_error", "pinn_kernel_time",
            "pinn_evaluate_scratch_bytes", "pinn_evaluate")
 
@@ -95,6 +95,8 @@ def lib():
     L.pinn_query.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_uint32, c_void_p,
                              c_void_p, c_size_t, c_void_p]
     L.pinn_exchange.restype = c_int32
+    L.pinn_query_noalloc.restype = c_int32
+    L.pinn_query_noalloc.argtypes = [c_void_p, c_void_p, c_int64, c_int32, c_uint32, c_void_p, c_void_p]
     L.pinn_exchange.argtypes = [c_void_p, POINTER(PinnFace), c_int32, POINTER(c_float),
                                 POINTER(c_void_p), c_void_p]
     L.pinn_kernel_time.restype = c_int32

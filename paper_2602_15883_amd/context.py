@@ -199,6 +199,15 @@ class Context:
                                _ptr(out) if n else None, sptr, sbytes, _stream(stream)))
         return out
 
+    def query_noalloc(self, x: torch.Tensor, out: torch.Tensor, sub: int = -1, what: str = "uvpw",
+                      stream=None) -> torch.Tensor:
+        """pinn_query_noalloc: the same query into the caller's `out`, routed
+        through the library-held scratch (no allocation anywhere)."""
+        n = x.shape[0]
+        check(lib().pinn_query_noalloc(self._h, _ptr(x) if n else None, n, sub, WHAT[what],
+                                       _ptr(out) if n else None, _stream(stream)))
+        return out
+
     # -------------------------------------------------------------- exchange
     def exchange(self, faces, x_anc, targets: List[Optional[torch.Tensor]], stream=None):
         """Write neighbour targets (u, p~) at ghost points (section 2.2);

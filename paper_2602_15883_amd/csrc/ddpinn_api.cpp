@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -42,6 +43,26 @@ pinn_status fail(pinn_status st, const char* fmt, ...) {
   } while (0)
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Device address of the library-held query scratch, one per device, resolved
+// at the first pinn_create on that device (with the device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+hipError_t resolve_noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = noalloc_scratch_address(&p);
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[device] = p;
+  }
+  *out = g_noalloc_ptr[device];
+  return hipSuccess;
+}
 
 int64_t nparams(int dim, int W, int H) {
   const int64_t D = dim + 1;
@@ -158,6 +179,7 @@ struct pinn_ctx {
   int n_sub = 0;
   std::vector<pinn_subdomain> subs;
   int device = 0, num_cu = 0;
+  void* noalloc_scratch = nullptr;   // device address of the library-held query scratch
   int tile_points = 16, value_points = 0;
   int threads = 0;
   int lds_floats = 0, qlds_floats = 0;
@@ -338,6 +360,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   const Shape& sh = c->sh;
 
   HIPCHECK(hipGetDevice(&c->device));
+  HIPCHECK(resolve_noalloc_scratch(c->device, &c->noalloc_scratch));
   HIPCHECK(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, c->device));
   int max_lds = 0, optin = 0;
   HIPCHECK(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
@@ -841,6 +864,20 @@ pinn_status pinn_query(pinn_ctx* c, const float* x, int64_t n, int32_t sub, uint
   const int64_t tiles = (n + npts - 1) / npts + c->n_sub;
   HIPCHECK(launch_query(qa, (int)std::min<int64_t>(tiles, max_wg), s));
   return PINN_OK;
+}
+
+pinn_status pinn_query_noalloc(pinn_ctx* c, const float* x, int64_t n, int32_t sub, uint32_t what, float* out,
+                               void* stream) {
+  g_err.clear();
+  if (!c) return fail(PINN_E_INVAL, "ctx is NULL");
+  if (sub == -1 && n > kNoallocQueryPoints)
+    return fail(PINN_E_BUDGET, "routed query of %lld points exceeds the %lld points of the library-held scratch",
+                (long long)n, (long long)kNoallocQueryPoints);
+  if (!c->noalloc_scratch) return fail(PINN_E_DEVICE, "library-held query scratch not resolved");
+  // the same launches as pinn_query, on the library-held scratch of this
+  // context's device (the scratch covers n <= kNoallocQueryPoints points and
+  // up to kMaxSub subdomains)
+  return pinn_query(c, x, n, sub, what, out, c->noalloc_scratch, kNoallocScratchBytes, stream);
 }
 
 pinn_status pinn_exchange(pinn_ctx* c, const pinn_face* faces, int32_t n_faces, const float* x_anc,

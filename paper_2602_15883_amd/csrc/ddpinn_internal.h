@@ -193,6 +193,16 @@ struct EvalArgs {
   int32_t D, n_snap, nblk, pad_;
 };
 
+// Routed-query scratch held by the library itself (pinn_query_noalloc): the
+// layout of pinn_query's caller scratch for up to kNoallocQueryPoints points
+// and kMaxSub subdomains (sub_id and perm [n], counts, cursor and offsets
+// [n_sub + 1], each part 256-byte aligned).
+constexpr int64_t kNoallocQueryPoints = int64_t(1) << 20;
+constexpr size_t kNoallocScratchBytes =
+    2 * ((4 * (size_t)kNoallocQueryPoints + 255) & ~size_t(255)) + 3 * ((4 * (size_t)(kMaxSub + 1) + 255) & ~size_t(255));
+// device address of the library-held scratch on the current device
+hipError_t noalloc_scratch_address(void** ptr);
+
 // Launchers (ddpinn_kernels.hip)
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int tile_points, int n_wg, hipStream_t s);

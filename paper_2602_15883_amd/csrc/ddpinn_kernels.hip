@@ -1990,6 +1990,15 @@ hipError_t launch_step(const StepArgs& a, int tile_points, int n_wg, hipStream_t
   return hipLaunchKernel(k, dim3(n_wg), block, args, lds, s);
 }
 
+// Routed-query scratch held by the library, for callers that cannot
+// allocate (pinn_query_noalloc).  Every GPU the library runs on holds its own
+// copy for the life of the process.  Host code never passes this name to a
+// kernel: the name is a host-side stand-in; the device address comes from
+// noalloc_scratch_address, resolved once per device with that device current.
+static __device__ __align__(256) char scratch[kNoallocScratchBytes];
+
+hipError_t noalloc_scratch_address(void** ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
+
 // the same launch with events tied to the dispatch itself: e0 takes the
 // kernel's start and e1 its end time stamp (either may be null)
 hipError_t launch_step_timed(const StepArgs& a, int tile_points, int n_wg, hipStream_t s, hipEvent_t e0,
