@@ -251,8 +251,17 @@ __device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]
 // map:  frag[((w*K4 + s4)*64 + lane)*4 + q] = W[16w + lane%16][kmap(4 s4 + q, lane/16)].
 // ---------------------------------------------------------------------------
 
-// acc[cb] += A(16 rows of this wave) * B(LDS [16*NCB cols][S], K = Wp)
-template <int NCB>
+// acc[cb] += A(16 rows of this wave) * B(LDS [16*NCB cols][S], K = Wp).
+// With TR the same operands enter the MFMA the other way round: the LDS
+// activations are the A operand and the weight fragment the B operand, so
+// acc[cb] holds the transposed tile (lane (g, j): column 16cb + 4g + i,
+// neuron 16w + j) from the same loads.
+template <bool TR>
+__device__ __forceinline__ v4f mfma_or(const float wf, const float act, v4f c) {
+  return TR ? mfma4(act, wf, c) : mfma4(wf, act, c);
+}
+
+template <int NCB, bool TR = false>
 __device__ __forceinline__ void mfma_step(const v4f a, const float* bb, int S, int s4, v4f (&acc)[NCB]) {
   v4f b[NCB];
 #pragma unroll
@@ -260,29 +269,29 @@ __device__ __forceinline__ void mfma_step(const v4f a, const float* bb, int S, i
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[q], b[cb][q], acc[cb]);
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma_or<TR>(a[q], b[cb][q], acc[cb]);
 }
 
 // the last, partial chunk: only its first KT K-steps hold neurons
-template <int NCB>
+template <int NCB, bool TR = false>
 __device__ __forceinline__ void mfma_tail(const v4f a, const float* bb, int S, int s4, int KT, v4f (&acc)[NCB]) {
   v4f b[NCB];
 #pragma unroll
   for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const v4f*>(bb + cb * 16 * S + 4 * s4);
 #pragma unroll
-  for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[0], b[cb][0], acc[cb]);
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma_or<TR>(a[0], b[cb][0], acc[cb]);
   if (KT > 1) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[1], b[cb][1], acc[cb]);
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma_or<TR>(a[1], b[cb][1], acc[cb]);
   }
   if (KT > 2) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma4(a[2], b[cb][2], acc[cb]);
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma_or<TR>(a[2], b[cb][2], acc[cb]);
   }
 }
 
 // K = 4*K4 + KT steps: K4 full chunks of four, then KT (0..3) more
-template <int NCB>
+template <int NCB, bool TR = false>
 __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const float* bufB,
                                           int S, int K4, int g, int j, int lane,
                                           v4f (&acc)[NCB], int KT) {
@@ -295,17 +304,17 @@ __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const
   int s4 = 0;
   for (; s4 + 2 <= K4; s4 += 2) {
     const v4f a1 = ldg4u(afrag + (s4 + 1) * 256, lo);
-    mfma_step<NCB>(a0, bb, S, s4, acc);
+    mfma_step<NCB, TR>(a0, bb, S, s4, acc);
     a0 = ldg4u(afrag + (s4 + 2 < KC ? s4 + 2 : s4 + 1) * 256, lo);
-    mfma_step<NCB>(a1, bb, S, s4 + 1, acc);
+    mfma_step<NCB, TR>(a1, bb, S, s4 + 1, acc);
   }
   if (s4 < K4) {
     const v4f a1 = KT ? ldg4u(afrag + (s4 + 1) * 256, lo) : a0;
-    mfma_step<NCB>(a0, bb, S, s4, acc);
+    mfma_step<NCB, TR>(a0, bb, S, s4, acc);
     a0 = a1;
     ++s4;
   }
-  if (KT) mfma_tail<NCB>(a0, bb, S, s4, KT, acc);
+  if (KT) mfma_tail<NCB, TR>(a0, bb, S, s4, KT, acc);
 }
 
 // dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col], t < NNB
@@ -340,6 +349,130 @@ __device__ __forceinline__ float sum16(float v) {
   v += __shfl_xor(v, 2, 16);
   v += __shfl_xor(v, 1, 16);
   return v;
+}
+
+// sum over the four lane groups (same j)
+__device__ __forceinline__ float sum_groups(float v) {
+  v += __shfl_xor(v, 16, 64);
+  v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Transposed tiles (the one-row-block step kernel).  Every GEMM of that kernel
+// enters its operands the other way round (gemm_rows<NCB, true>), so a wave's
+// accumulator fragment acc[cb] holds, in lane (g, j), neuron 16w + j of
+// columns 16cb + 4g + i (i = 0..3).  Every channel of a (neuron, point) pair
+// still sits in one lane (column block cb = channel), so the chain rule runs
+// in registers as before, and the weight gradient
+//   dW_l[16w + m][n] = sum_col Zbar_l[16w + m][col] H_{l-1}[n][col]
+// takes its A operand (Zbar_l of this wave's neurons, K = columns) straight
+// from the registers: step (cb, i) pairs lane (g, j)'s acc[cb][i] with
+// column 16cb + 4g + i.  Only H_{l-1} comes from LDS, four columns per
+// ds_read_b128.
+// ---------------------------------------------------------------------------
+
+// input layer: z0 = W1 xi + b1 and the seeded channels, transposed tile
+template <int DIM, int NCB, int MODE>
+__device__ __forceinline__ void input_layer_t(v4f (&a)[NCB], const float* __restrict__ W1p,
+                                              const float* __restrict__ b1p, const float* xin,
+                                              int w, int g, int j) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int D = DIM + 1, NPB = M::NPB;
+  const int r = 16 * w + j;
+  float wr[D];
+#pragma unroll
+  for (int q = 0; q < D; ++q) wr[q] = ldg(W1p + r * D + q);
+  const float br = ldg(b1p + r);
+#pragma unroll
+  for (int pb = 0; pb < NPB; ++pb) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float* xp = xin + (16 * pb + 4 * g + i) * D;
+      float z = br;
+#pragma unroll
+      for (int q = 0; q < D; ++q) z += wr[q] * xp[q];
+      a[pb][i] = z;
+    }
+    if constexpr (MODE == M_PDE) {
+#pragma unroll
+      for (int jj = 0; jj <= DIM; ++jj) a[(1 + jj) * NPB + pb] = v4f{wr[jj], wr[jj], wr[jj], wr[jj]};
+#pragma unroll
+      for (int jj = 0; jj < DIM; ++jj) a[(DIM + 2 + jj) * NPB + pb] = zero4();
+    } else if constexpr (MODE == M_GRAD) {
+#pragma unroll
+      for (int jj = 0; jj < DIM; ++jj) a[(1 + jj) * NPB + pb] = v4f{wr[jj], wr[jj], wr[jj], wr[jj]};
+    }
+  }
+}
+
+// add the bias of this lane's neuron to the value-channel column blocks
+template <int NCB, int NPB>
+__device__ __forceinline__ void add_bias_t(v4f (&a)[NCB], const float* __restrict__ b, int w, int j) {
+  const float bv = ldg(b + 16 * w + j);
+#pragma unroll
+  for (int pb = 0; pb < NPB; ++pb) a[pb] += bv;
+}
+
+// store a transposed fragment into the LDS layout [col][neuron] (stride S)
+template <int NCB>
+__device__ __forceinline__ void store_fwd_t(float* buf, int S, const v4f (&a)[NCB], int w, int g, int j) {
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) buf[(16 * cb + 4 * g + i) * S + 16 * w + j] = a[cb][i];
+}
+
+// h = act(z) of a stashed (transposed) pre-activation stack, written into the
+// neuron-major LDS layout [neuron][col] (stride S2): four columns per store
+template <int DIM, int NCB, int MODE, int ACT>
+__device__ __forceinline__ void act_store_bwd_t(float* buf, int S2, const v4f (&z)[NCB], int w, int g, int j) {
+  using M = ModeCfg<DIM, NCB, MODE>;
+  constexpr int NPB = M::NPB;
+  float* row = buf + (16 * w + j) * S2 + 4 * g;
+#pragma unroll
+  for (int pb = 0; pb < NPB; ++pb) {
+    // activation derivatives of the four columns first, then one channel
+    // at a time into a four-column store (few values live at once)
+    v4f sv, s1, s2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float a0, a1, a2;
+      act_d2<ACT>(z[pb][i], a0, a1, a2);
+      sv[i] = a0;
+      s1[i] = a1;
+      s2[i] = a2;
+    }
+    *reinterpret_cast<v4f*>(row + 16 * pb) = sv;
+    if constexpr (MODE == M_PDE) {
+#pragma unroll
+      for (int jj = 0; jj <= DIM; ++jj)
+        *reinterpret_cast<v4f*>(row + 16 * ((1 + jj) * NPB + pb)) = s1 * z[(1 + jj) * NPB + pb];
+#pragma unroll
+      for (int jj = 0; jj < DIM; ++jj) {
+        const v4f z1 = z[(1 + jj) * NPB + pb];
+        *reinterpret_cast<v4f*>(row + 16 * ((DIM + 2 + jj) * NPB + pb)) = s2 * z1 * z1 + s1 * z[(DIM + 2 + jj) * NPB + pb];
+      }
+    }
+  }
+}
+
+// dw[t] += Zbar(this wave's neurons, registers) * Hprev[16(nb0+t) + n][.]^T
+//   Hprev from bufHb ([neuron][col], stride S2); K = the tile's columns
+template <int NCB, int NNB>
+__device__ __forceinline__ void gemm_dw_t(const v4f (&zb)[NCB], const float* bufHb, int S2, int g, int j,
+                                          int nb0, v4f (&dw)[4]) {
+  const float* bb = bufHb + (16 * nb0 + j) * S2 + 4 * g;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) {
+    v4f b[NNB];
+#pragma unroll
+    for (int t = 0; t < NNB; ++t) b[t] = *reinterpret_cast<const v4f*>(bb + t * 16 * S2 + 16 * cb);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int t = 0; t < NNB; ++t) dw[t] = mfma4(zb[cb][i], b[t][i], dw[t]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -450,10 +583,17 @@ struct StepLds {
   int bufH, bufG, ys, yb, xin, acc1, dbacc, red, sched, total;
 };
 
-__host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB) {
+// Row stride of the [col][neuron] stacks of the one-row-block kernels: a
+// compile-time constant per kernel instance (68, 100 or 132 floats, the
+// smallest that holds Wp + 4), so every LDS address of a tile is one lane
+// base plus an immediate offset.  Each is 4 mod 32, which keeps the operand
+// reads and stores free of bank conflicts.
+__host__ __device__ inline int step_row_stride(int Wp) { return Wp <= 64 ? 68 : (Wp <= 96 ? 100 : 132); }
+
+__host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB, int S = 0) {
   StepLds L;
   L.NCOL = 16 * NCB;
-  L.S = Wp + 4;
+  L.S = S ? S : Wp + 4;
   L.S2 = L.NCOL + 4;
   const int hsz = (L.NCOL * L.S > Wp * L.S2) ? L.NCOL * L.S : Wp * L.S2;
   int o = 0;
@@ -564,9 +704,9 @@ __device__ __forceinline__ void adjoint_rows(v4f (&acc)[NCB], const v4f (&zs)[NC
 }
 
 template <int SPLIT>
-__host__ __device__ inline StepLds step_plan(int D, int Wp, int H, int NCB) {
+__host__ __device__ inline StepLds step_plan(int D, int Wp, int H, int NCB, int S = 0) {
   if constexpr (SPLIT) return step_lds_split(D, Wp, H, NCB);
-  else return step_lds(D, Wp, H, NCB);
+  else return step_lds(D, Wp, H, NCB, S);
 }
 
 // h = act(z) of a stashed pre-activation stack, only the column blocks
@@ -638,7 +778,9 @@ __device__ __forceinline__ void dw_tiles(float* sw, bool first, const float* buf
 // ---------------------------------------------------------------------------
 // Fused step kernel: persistent over this workgroup's item range.
 // ---------------------------------------------------------------------------
-template <int DIM, int PBP, int ACT, int RPW, int SPLIT>
+// SS: the row stride of the [col][neuron] stacks when fixed per instance (the
+// one-row-block kernels), 0 when it is Wp + 4 (two row blocks per wave)
+template <int DIM, int PBP, int ACT, int RPW, int SPLIT, int SS>
 __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepArgs args) {
   constexpr int D = DIM + 1;
   constexpr int CF = 2 * DIM + 2;
@@ -656,7 +798,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   // lets every per-wave address (weights, stash, slab) be a scalar base plus
   // the lane offset instead of a 64-bit vector address per use
   const int lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4, j = lane & 15;
-  const StepLds L = step_plan<SPLIT>(D, Wp, H, NCB);
+  const StepLds L = step_plan<SPLIT>(D, Wp, H, NCB, SS);
   float* bufH = lds + L.bufH;
   float* bufG = lds + L.bufG;
   float* ys = lds + L.ys;
@@ -665,7 +807,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   float* acc1 = lds + L.acc1;
   float* dbacc = lds + L.dbacc;
   float* red = lds + L.red;
-  const int S = L.S, S2 = L.S2;
+  const int S = SS ? SS : L.S, S2 = L.S2;
 
   // row blocks of this wave: w, and w + NWV when there are more than NWV
   const int nrb = (RPW == 1) ? 1 : (w + NWV < NW ? 2 : 1);
@@ -753,13 +895,13 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     float* hin = bufH;
     float* hout = bufG;
     if constexpr (RPW == 1) {
-      if (pde) input_layer<DIM, NCB, M_PDE>(acc, W1p, bp, xin, w, g, j);
-      else input_layer<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
+      if (pde) input_layer_t<DIM, NCB, M_PDE>(acc, W1p, bp, xin, w, g, j);
+      else input_layer_t<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + (0 * NCB + cb) * 256, lo16, acc[cb]);
       if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
       else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
-      store_fwd<NCB>(hin, S, acc, w, g, j);
+      store_fwd_t<NCB>(hin, S, acc, w, g, j);
       __syncthreads();
 
       // ---- forward: hidden layers 2..H
@@ -771,15 +913,15 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         // the older one, which then idles at the next barrier while the younger
         // finishes.  Raising the younger half's priority for the GEMM evens them.
         if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-        gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc, KT);
+        gemm_rows<NCB, true>(Wf, hin, S, K4, g, j, lane, acc, KT);
         __builtin_amdgcn_s_setprio(0);
-        if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, g);
-        else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, g);
+        if (pde) add_bias_t<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, j);
+        else add_bias_t<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, j);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16, acc[cb]);
         if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
         else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
-        store_fwd<NCB>(hout, S, acc, w, g, j);
+        store_fwd_t<NCB>(hout, S, acc, w, g, j);
         __syncthreads();
         float* t = hin;
         hin = hout;
@@ -983,68 +1125,67 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           for (int col = 0; col < 16 * npb; ++col) s += yb[tid * NCOL + col];
           dbo += s;
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int r = 16 * w + 4 * g + i;
+        {
+          // lane (g, j): neuron 16w + j of columns 16cb + 4g + i (transposed tile)
           float wo[D];
 #pragma unroll
-          for (int o = 0; o < D; ++o) wo[o] = ldg(Wop + o * Wp + r);
+          for (int o = 0; o < D; ++o) wo[o] = ldg(Wop + o * Wp + 16 * w + j);
 #pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) {
-            float s = 0.f;
+          for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-            for (int o = 0; o < D; ++o) s += wo[o] * yb[o * NCOL + 16 * cb + j];
-            acc[cb][i] = s;
-          }
+            for (int i = 0; i < 4; ++i) {
+              float s = 0.f;
+#pragma unroll
+              for (int o = 0; o < D; ++o) s += wo[o] * yb[o * NCOL + 16 * cb + 4 * g + i];
+              acc[cb][i] = s;
+            }
         }
       }
 
-      // ---- hidden and input layer adjoints
+      // ---- hidden and input layer adjoints (transposed tiles)
       for (int l = H; l >= 1; --l) {
         if (pde) act_adjoint<DIM, NCB, M_PDE, ACT>(acc, zs);
         else act_adjoint<DIM, NCB, M_VALUE, ACT>(acc, zs);
-        // db_l: value-channel columns
+        // db_l: value-channel columns of this lane's neuron
         {
           const int npb = pde ? MP::NPB : MV::NPB;
+          float s = 0.f;
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            float s = 0.f;
-#pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
-              if (cb < npb) s += acc[cb][i];
-            s = sum16(s);
-            if (j == 0) dbacc[(l - 1) * Wp + 16 * w + 4 * g + i] += s;
-          }
+          for (int cb = 0; cb < NCB; ++cb)
+            if (cb < npb) s += (acc[cb][0] + acc[cb][1]) + (acc[cb][2] + acc[cb][3]);
+          s = sum_groups(s);
+          if (g == 0) dbacc[(l - 1) * Wp + 16 * w + j] += s;
         }
         if (l == 1) {
           // input layer: dW1[r][q] += sum_pts zbar0 xi_q + zbar_q (first-derivative channel q)
+          const int r = 16 * w + j;
+          float v[D];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = 16 * w + 4 * g + i;
-            float v[D];
+          for (int q = 0; q < D; ++q) v[q] = 0.f;
+          if (pde) {
 #pragma unroll
-            for (int q = 0; q < D; ++q) v[q] = 0.f;
-            if (pde) {
+            for (int pb = 0; pb < MP::NPB; ++pb)
 #pragma unroll
-              for (int pb = 0; pb < MP::NPB; ++pb) {
-                const float* xp = xin + (16 * pb + j) * D;
+              for (int i = 0; i < 4; ++i) {
+                const float* xp = xin + (16 * pb + 4 * g + i) * D;
 #pragma unroll
                 for (int q = 0; q < D; ++q)
                   v[q] += acc[pb][i] * xp[q] + acc[(1 + q) * MP::NPB + pb][i];
               }
-            } else {
+          } else {
 #pragma unroll
-              for (int cb = 0; cb < NCB; ++cb) {
-                const float* xp = xin + (16 * cb + j) * D;
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const float* xp = xin + (16 * cb + 4 * g + i) * D;
 #pragma unroll
                 for (int q = 0; q < D; ++q) v[q] += acc[cb][i] * xp[q];
               }
-            }
+          }
 #pragma unroll
-            for (int q = 0; q < D; ++q) {
-              const float s = sum16(v[q]);
-              if (j == 0) acc1[r * D + q] += s;
-            }
+          for (int q = 0; q < D; ++q) {
+            const float s = sum_groups(v[q]);
+            if (g == 0) acc1[r * D + q] += s;
           }
           break;
         }
@@ -1054,13 +1195,14 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         for (int cb = 0; cb < NCB; ++cb)
           zs[cb] = ldg4u(stash_w + ((l - 2) * NCB + cb) * 256, lo16);
         __syncthreads();
-        store_fwd<NCB>(bufG, S, acc, w, g, j);
+        store_fwd_t<NCB>(bufG, S, acc, w, g, j);
         // recompute h_{l-1} from z_{l-1}
-        if (pde) act_store_bwd<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w, g, j);
-        else act_store_bwd<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w, g, j);
+        if (pde) act_store_bwd_t<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w, g, j);
+        else act_store_bwd_t<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w, g, j);
         __syncthreads();
-        // dW_l += Zbar_l H_{l-1}^T into this segment's slab; the slab's current
-        // values are requested before each chunk's GEMM so the read overlaps it
+        // dW_l += Zbar_l H_{l-1}^T into this segment's slab, Zbar_l from the
+        // registers; the slab's current values are requested before each
+        // chunk's GEMM so the read overlaps it
         {
           float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
           const bool first = item.flags & ITEM_FIRST;
@@ -1073,10 +1215,10 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
               old[t] = (t < nnb && !first) ? ldg4u(sw + (size_t)(w * NW + nb0 + t) * 256, lo16) : zero4();
             v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
             switch (nnb) {
-              case 4: gemm_dw<NCB, 4>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
-              case 3: gemm_dw<NCB, 3>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
-              case 2: gemm_dw<NCB, 2>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
-              default: gemm_dw<NCB, 1>(bufG, S, bufH, S2, w, g, j, nb0, dw); break;
+              case 4: gemm_dw_t<NCB, 4>(acc, bufH, S2, g, j, nb0, dw); break;
+              case 3: gemm_dw_t<NCB, 3>(acc, bufH, S2, g, j, nb0, dw); break;
+              case 2: gemm_dw_t<NCB, 2>(acc, bufH, S2, g, j, nb0, dw); break;
+              default: gemm_dw_t<NCB, 1>(acc, bufH, S2, g, j, nb0, dw); break;
             }
 #pragma unroll
             for (int t = 0; t < 4; ++t)
@@ -1090,7 +1232,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
           const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
           if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-          gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc, KT);
+          gemm_rows<NCB, true>(WT, bufG, S, K4, g, j, lane, acc, KT);
           __builtin_amdgcn_s_setprio(0);
         }
       }
@@ -1926,9 +2068,12 @@ int step_value_points(int dim, int tile_points) {
   return 16 * (2 * dim + 2) * (tile_points / 16);
 }
 
+static int rows_per_wave(const Shape& sh) { return sh.NW > sh.NWV ? 2 : 1; }
+
 int step_lds_floats(const Shape& sh, int tile_points) {
   const int NCB = (2 * sh.dim + 2) * (tile_points / 16);
-  return sh.split ? step_lds_split(sh.D, sh.Wp, sh.H, NCB).total : step_lds(sh.D, sh.Wp, sh.H, NCB).total;
+  if (sh.split) return step_lds_split(sh.D, sh.Wp, sh.H, NCB).total;
+  return step_lds(sh.D, sh.Wp, sh.H, NCB, rows_per_wave(sh) == 1 ? step_row_stride(sh.Wp) : 0).total;
 }
 
 int query_lds_floats(const Shape& sh, int small) {
@@ -1938,22 +2083,30 @@ int query_lds_floats(const Shape& sh, int small) {
 // Kernel instances: dimension, tile (16 or 32 collocation points), activation,
 // row blocks per wave (2 above 8 row blocks; 16-point tiles only) and, for two
 // row blocks, the column-split LDS plan.
+template <int DIM, int PBP, int SS>
+static const void* step_ptr_act(int act) {
+  return act == ACT_SIN ? (const void*)step_kernel<DIM, PBP, ACT_SIN, 1, 0, SS>
+                        : (const void*)step_kernel<DIM, PBP, ACT_TANH, 1, 0, SS>;
+}
 template <int DIM>
-static const void* step_ptr_dim(int tile_points, int act, int rpw, int split) {
+static const void* step_ptr_dim(int tile_points, int act, int rpw, int split, int Wp) {
   if (rpw == 2) {
-    if (split) return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 1> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 1>;
-    return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 0> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 0>;
+    if (split) return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 1, 0> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 1, 0>;
+    return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 0, 0> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 0, 0>;
   }
-  if (tile_points == 32) return act == ACT_SIN ? (const void*)step_kernel<DIM, 2, ACT_SIN, 1, 0> : (const void*)step_kernel<DIM, 2, ACT_TANH, 1, 0>;
-  return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 1, 0> : (const void*)step_kernel<DIM, 1, ACT_TANH, 1, 0>;
+  if (tile_points == 32) return Wp <= 64 ? step_ptr_act<DIM, 2, 68>(act) : nullptr;
+  switch (step_row_stride(Wp)) {
+    case 68: return step_ptr_act<DIM, 1, 68>(act);
+    case 100: return step_ptr_act<DIM, 1, 100>(act);
+    default: return step_ptr_act<DIM, 1, 132>(act);
+  }
 }
-static const void* step_ptr(int dim, int tile_points, int act, int rpw, int split) {
-  return dim == 2 ? step_ptr_dim<2>(tile_points, act, rpw, split) : step_ptr_dim<3>(tile_points, act, rpw, split);
+static const void* step_ptr(int dim, int tile_points, int act, int rpw, int split, int Wp) {
+  return dim == 2 ? step_ptr_dim<2>(tile_points, act, rpw, split, Wp) : step_ptr_dim<3>(tile_points, act, rpw, split, Wp);
 }
-static int rows_per_wave(const Shape& sh) { return sh.NW > sh.NWV ? 2 : 1; }
 const void* step_kernel_ptr(const Shape& sh, int tile_points) {
   if (rows_per_wave(sh) == 2 && tile_points != 16) return nullptr;
-  return step_ptr(sh.dim, tile_points, sh.act, rows_per_wave(sh), sh.split);
+  return step_ptr(sh.dim, tile_points, sh.act, rows_per_wave(sh), sh.split, sh.Wp);
 }
 const void* prep_kernel_ptr() { return (const void*)prep_kernel; }
 const void* slab_sum_kernel_ptr() { return (const void*)slab_sum_kernel; }
@@ -2090,10 +2243,10 @@ hipError_t set_lds_limits(int bytes) {
   };
   for (int dim = 2; dim <= 3; ++dim)
     for (int act = ACT_TANH; act <= ACT_SIN; ++act) {
-      allow(step_ptr(dim, 16, act, 1, 0));
-      allow(step_ptr(dim, 32, act, 1, 0));
-      allow(step_ptr(dim, 16, act, 2, 0));
-      allow(step_ptr(dim, 16, act, 2, 1));
+      for (int wp : {64, 96, 128}) allow(step_ptr(dim, 16, act, 1, 0, wp));
+      allow(step_ptr(dim, 32, act, 1, 0, 64));
+      allow(step_ptr(dim, 16, act, 2, 0, 0));
+      allow(step_ptr(dim, 16, act, 2, 1, 0));
       for (int rpw = 1; rpw <= 2; ++rpw) {
         for (int mode : {M_PDE, M_VALUE, M_GRAD}) {
           allow(query_ptr(dim, mode, act, rpw, 0));
