@@ -1201,18 +1201,22 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         else act_store_bwd_t<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w, g, j);
         __syncthreads();
         // dW_l += Zbar_l H_{l-1}^T into this segment's slab, Zbar_l from the
-        // registers; the slab's current values are requested before each
-        // chunk's GEMM so the read overlaps it
+        // registers (at most 8 column blocks: widths up to 128); the slab's
+        // current values are requested before the GEMMs so the reads overlap them
         {
           float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
           const bool first = item.flags & ITEM_FIRST;
           if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);   // as in the forward GEMM
+          // the current slab values of both groups are requested up front
+          v4f old8[8];
+#pragma unroll
+          for (int t = 0; t < 8; ++t)
+            old8[t] = (t < NW && !first) ? ldg4u(sw + (size_t)(w * NW + t) * 256, lo16) : zero4();
           for (int nb0 = 0; nb0 < NW; nb0 += 4) {
             const int nnb = (NW - nb0) < 4 ? (NW - nb0) : 4;
             v4f old[4];
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-              old[t] = (t < nnb && !first) ? ldg4u(sw + (size_t)(w * NW + nb0 + t) * 256, lo16) : zero4();
+            for (int t = 0; t < 4; ++t) old[t] = nb0 == 0 ? old8[t] : old8[4 + t];
             v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
             switch (nnb) {
               case 4: gemm_dw_t<NCB, 4>(acc, bufH, S2, g, j, nb0, dw); break;
