@@ -583,12 +583,16 @@ struct StepLds {
   int bufH, bufG, ys, yb, xin, acc1, dbacc, red, sched, total;
 };
 
-// Row stride of the [col][neuron] stacks of the one-row-block kernels: a
+// Row stride of the [col][neuron] stacks.  Up to 128 neurons it is a
 // compile-time constant per kernel instance (68, 100 or 132 floats, the
-// smallest that holds Wp + 4), so every LDS address of a tile is one lane
-// base plus an immediate offset.  Each is 4 mod 32, which keeps the operand
-// reads and stores free of bank conflicts.
-__host__ __device__ inline int step_row_stride(int Wp) { return Wp <= 64 ? 68 : (Wp <= 96 ? 100 : 132); }
+// smallest that holds Wp + 4); above, Wp + 4, a compile-time constant for the
+// paper's cylinder widths (Wp = 160 and 208) and a kernel argument for the
+// others.  A constant stride makes every LDS address of a tile one lane base
+// plus an immediate offset.  With each stride the rows that one operand read
+// or store touches fall in distinct banks.
+__host__ __device__ inline int step_row_stride(int Wp) {
+  return Wp <= 64 ? 68 : (Wp <= 96 ? 100 : (Wp <= 128 ? 132 : Wp + 4));
+}
 
 __host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB, int S = 0) {
   StepLds L;
@@ -614,10 +618,10 @@ __host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB, int S
 // plan above does not fit): the forward keeps one activation stack [NCOL][S]
 // at bufG; the backward holds Zbar [NCOL/2][S] at bufG and H_{l-1}
 // [Wp][NCOL/2 + 4] at bufH for one half of the tile's columns at a time.
-__host__ __device__ inline StepLds step_lds_split(int D, int Wp, int H, int NCB) {
+__host__ __device__ inline StepLds step_lds_split(int D, int Wp, int H, int NCB, int S = 0) {
   StepLds L;
   L.NCOL = 16 * NCB;
-  L.S = Wp + 4;
+  L.S = S ? S : Wp + 4;
   L.S2 = L.NCOL / 2 + 4;
   const int zh = ((L.NCOL / 2) * L.S + 3) & ~3;
   const int bwd = zh + Wp * L.S2;
@@ -705,7 +709,7 @@ __device__ __forceinline__ void adjoint_rows(v4f (&acc)[NCB], const v4f (&zs)[NC
 
 template <int SPLIT>
 __host__ __device__ inline StepLds step_plan(int D, int Wp, int H, int NCB, int S = 0) {
-  if constexpr (SPLIT) return step_lds_split(D, Wp, H, NCB);
+  if constexpr (SPLIT) return step_lds_split(D, Wp, H, NCB, S);
   else return step_lds(D, Wp, H, NCB, S);
 }
 
@@ -778,8 +782,7 @@ __device__ __forceinline__ void dw_tiles(float* sw, bool first, const float* buf
 // ---------------------------------------------------------------------------
 // Fused step kernel: persistent over this workgroup's item range.
 // ---------------------------------------------------------------------------
-// SS: the row stride of the [col][neuron] stacks when fixed per instance (the
-// one-row-block kernels), 0 when it is Wp + 4 (two row blocks per wave)
+// SS: the row stride of the [col][neuron] stacks (step_row_stride)
 template <int DIM, int PBP, int ACT, int RPW, int SPLIT, int SS>
 __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepArgs args) {
   constexpr int D = DIM + 1;
@@ -2076,8 +2079,8 @@ static int rows_per_wave(const Shape& sh) { return sh.NW > sh.NWV ? 2 : 1; }
 
 int step_lds_floats(const Shape& sh, int tile_points) {
   const int NCB = (2 * sh.dim + 2) * (tile_points / 16);
-  if (sh.split) return step_lds_split(sh.D, sh.Wp, sh.H, NCB).total;
-  return step_lds(sh.D, sh.Wp, sh.H, NCB, rows_per_wave(sh) == 1 ? step_row_stride(sh.Wp) : 0).total;
+  if (sh.split) return step_lds_split(sh.D, sh.Wp, sh.H, NCB, step_row_stride(sh.Wp)).total;
+  return step_lds(sh.D, sh.Wp, sh.H, NCB, step_row_stride(sh.Wp)).total;
 }
 
 int query_lds_floats(const Shape& sh, int small) {
@@ -2092,11 +2095,19 @@ static const void* step_ptr_act(int act) {
   return act == ACT_SIN ? (const void*)step_kernel<DIM, PBP, ACT_SIN, 1, 0, SS>
                         : (const void*)step_kernel<DIM, PBP, ACT_TANH, 1, 0, SS>;
 }
+template <int DIM, int SS>
+static const void* step_ptr_wide(int act, int split) {
+  if (split) return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 1, SS> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 1, SS>;
+  return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 0, SS> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 0, SS>;
+}
 template <int DIM>
 static const void* step_ptr_dim(int tile_points, int act, int rpw, int split, int Wp) {
   if (rpw == 2) {
-    if (split) return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 1, 0> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 1, 0>;
-    return act == ACT_SIN ? (const void*)step_kernel<DIM, 1, ACT_SIN, 2, 0, 0> : (const void*)step_kernel<DIM, 1, ACT_TANH, 2, 0, 0>;
+    switch (Wp) {
+      case 160: return step_ptr_wide<DIM, 164>(act, split);
+      case 208: return step_ptr_wide<DIM, 212>(act, split);
+      default: return step_ptr_wide<DIM, 0>(act, split);
+    }
   }
   if (tile_points == 32) return Wp <= 64 ? step_ptr_act<DIM, 2, 68>(act) : nullptr;
   switch (step_row_stride(Wp)) {
@@ -2249,8 +2260,10 @@ hipError_t set_lds_limits(int bytes) {
     for (int act = ACT_TANH; act <= ACT_SIN; ++act) {
       for (int wp : {64, 96, 128}) allow(step_ptr(dim, 16, act, 1, 0, wp));
       allow(step_ptr(dim, 32, act, 1, 0, 64));
-      allow(step_ptr(dim, 16, act, 2, 0, 0));
-      allow(step_ptr(dim, 16, act, 2, 1, 0));
+      for (int wp : {160, 208, 256}) {   // the two constant strides and the argument
+        allow(step_ptr(dim, 16, act, 2, 0, wp));
+        allow(step_ptr(dim, 16, act, 2, 1, wp));
+      }
       for (int rpw = 1; rpw <= 2; ++rpw) {
         for (int mode : {M_PDE, M_VALUE, M_GRAD}) {
           allow(query_ptr(dim, mode, act, rpw, 0));
