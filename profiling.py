@@ -3,13 +3,15 @@ HBM traffic scaled by a copy-kernel calibration).
 
 Usage (on the host that holds the rocprofv3 output directories):
 
-  python profiling.py stats  TRACE_DIR  OUT.md  "command"
+  python profiling.py stats  TRACE_DIR  OUT.md  "command" [PLAIN_GROUPS]
   python profiling.py counters OUT.md "command" DIR...
   python profiling.py traffic WORKLOAD FETCH_DIR WRITE_DIR COPY_BYTES
 
 `stats` also lists, from the per-dispatch trace, each kernel's median
 duration and its mean over the launches after the first few (the first
-launches of a run are slower: cold caches and clocks).
+launches of a run are slower: cold caches and clocks); with PLAIN_GROUPS = n
+it also compares the grouped step-kernel launches with the runs of n plain
+per-subdomain launches between them.
 
 `traffic` scales each counter by (bytes the calibration copy really moved) /
 (what the same counter reported for it), and records the result with the
@@ -70,6 +72,21 @@ def dispatch_durations(trace_dir: str):
     return out
 
 
+def step_dispatches_by_grid(trace_dir: str):
+    """{(step kernel name, grid threads): [duration ns, ...]} in dispatch order"""
+    out = defaultdict(list)
+    for path in _csvs(trace_dir, "kernel_trace.csv"):
+        rows = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if STEP_KERNEL in r["Kernel_Name"]:
+                    rows.append((int(r["Start_Timestamp"]), r["Kernel_Name"], int(r["Grid_Size_X"]),
+                                 int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        for _t, name, grid, d in sorted(rows):
+            out[(name, grid)].append(d)
+    return out
+
+
 def counter_values(d: str):
     """{kernel name: {counter: [values per dispatch]}}"""
     out = defaultdict(lambda: defaultdict(list))
@@ -87,7 +104,7 @@ def _find(kv, sub):
     return None
 
 
-def write_stats_md(trace_dir, out_md, command, skip_first=3):
+def write_stats_md(trace_dir, out_md, command, skip_first=3, plain_groups=0):
     rows = stats(trace_dir)
     durs = dispatch_durations(trace_dir)
     lines = [f"# Kernel time: {os.path.basename(out_md)[:-3]}", "",
@@ -106,6 +123,50 @@ def write_stats_md(trace_dir, out_md, command, skip_first=3):
                      f"{med} | {mt} | "
                      f"{float(r['MinNs']) / 1e3:.1f} | {float(r['MaxNs']) / 1e3:.1f} | "
                      f"{float(r['Percentage']):.2f} |")
+    if plain_groups:
+        # grouped launches alternate with runs of plain_groups per-subdomain
+        # launches of the same kernel: a dispatch is part of a run when its
+        # neighbours are, i.e. split the sequence at the long (grouped) ones
+        seq_all = []
+        for path in _csvs(trace_dir, "kernel_trace.csv"):
+            with open(path) as f:
+                seq_all += [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                            for r in csv.DictReader(f) if STEP_KERNEL in r["Kernel_Name"]]
+        seq_all.sort()
+        durs = [e - b for b, e in seq_all]
+        cut = (max(durs) + min(durs)) / 2
+        runs, cur = [], []
+        grouped = []
+        for d in durs:
+            if d > cut:
+                if len(cur) == plain_groups:
+                    runs.append(cur)
+                cur = []
+                grouped.append(d)
+            else:
+                cur.append(d)
+        if len(cur) == plain_groups:
+            runs.append(cur)
+        sums = sorted(sum(r) for r in runs)
+        gs = sorted(grouped)
+        if sums and gs:
+            lines += ["", f"Grouped launch vs {plain_groups} plain per-subdomain launches (the step kernel's "
+                      f"dispatches split at {cut / 1e3:.0f} us; plain launches summed per step, kernel "
+                      "execution only):", "",
+                      "| Launch | Steps | Median (us) |", "|---|---|---|",
+                      f"| one grouped launch | {len(gs)} | {gs[len(gs) // 2] / 1e3:.1f} |",
+                      f"| {plain_groups} plain launches (sum) | {len(sums)} | {sums[len(sums) // 2] / 1e3:.1f} |",
+                      f"| ratio plain / grouped | | {sums[len(sums) // 2] / gs[len(gs) // 2]:.3f} |"]
+    by_grid = step_dispatches_by_grid(trace_dir)
+    if len(by_grid) > 1:
+        lines += ["", "Step-kernel dispatches by grid size (workgroups x threads):", "",
+                  "| Kernel | Grid threads | Calls | Median (us) | Mean after " + str(skip_first) + " (us) |",
+                  "|---|---|---|---|---|"]
+        for (name, grid), d in sorted(by_grid.items(), key=lambda kv: -kv[0][1]):
+            ds = sorted(d)
+            tail = d[skip_first:]
+            mt = f"{sum(tail) / len(tail) / 1e3:.1f}" if tail else "-"
+            lines.append(f"| `{short(name)}` | {grid} | {len(d)} | {ds[len(ds) // 2] / 1e3:.1f} | {mt} |")
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")
     return rows
@@ -164,7 +225,8 @@ def traffic(workload, fetch_dir, write_dir, copy_bytes, out_json=None):
 if __name__ == "__main__":
     cmd = sys.argv[1]
     if cmd == "stats":
-        for r in write_stats_md(sys.argv[2], sys.argv[3], sys.argv[4]):
+        pg = int(sys.argv[5]) if len(sys.argv) > 5 else 0
+        for r in write_stats_md(sys.argv[2], sys.argv[3], sys.argv[4], plain_groups=pg):
             print(r["Name"][:60], r["Calls"], r["AverageNs"])
     elif cmd == "counters":
         print(write_counters_md(sys.argv[2], sys.argv[3], sys.argv[4:]))
