@@ -279,7 +279,7 @@ def launch_shape(args, pb, name, P):
         return shape, "tuned now"
     e = tune.lookup(key)
     if e:
-        return {"tile_points": e["tile_points"], "blocks_per_cu": e["blocks_per_cu"]}, "tuning table"
+        return tune.shape_of(e), "tuning table"
     return {}, "library default"
 
 

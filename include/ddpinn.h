@@ -106,6 +106,12 @@ typedef struct {
                              norm before Adam (section 3.3: 1.0); 0 = off     */
   float lr_factor;        /* step decay: lr_t = lr * lr_factor^floor((t-1) /  */
   int32_t lr_interval;    /*   lr_interval) (appendix B); interval 0 = off    */
+  int32_t gemm_priority_off; /* launch knob: 0 = the younger half of each
+                             workgroup's waves raises its priority for its
+                             GEMMs (default), 1 = all waves at one priority */
+  int32_t ranges_per_wg;  /* launch knob: item ranges per persistent
+                             workgroup when several workgroups share a
+                             compute unit (taken in turn); 0 = 4, 1..64     */
 } pinn_config;
 
 typedef struct {

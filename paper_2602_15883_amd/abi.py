@@ -48,7 +48,8 @@ class PinnConfig(ctypes.Structure):
                 ("lam", c_float * 6), ("lr", c_float), ("beta1", c_float), ("beta2", c_float),
                 ("eps", c_float), ("tile_points", c_int32), ("blocks_per_cu", c_int32),
                 ("max_query_points", c_int64), ("comp_w", c_float * 3), ("clip_norm", c_float),
-                ("lr_factor", c_float), ("lr_interval", c_int32)]
+                ("lr_factor", c_float), ("lr_interval", c_int32), ("gemm_priority_off", c_int32),
+                ("ranges_per_wg", c_int32)]
 
 
 class PinnSubdomain(ctypes.Structure):

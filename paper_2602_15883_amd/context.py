@@ -84,6 +84,7 @@ class Context:
                  blocks_per_cu: int = 0, max_query_points: int = 1 << 22,
                  activation: str = "tanh", comp_w=None, clip_norm: float = 0.0,
                  lr_factor: float = 1.0, lr_interval: int = 0,
+                 gemm_priority: bool = True, ranges_per_wg: int = 0,
                  device=None, stream=None):
         if not torch.cuda.is_available():
             raise RuntimeError("libddpinn needs a ROCm GPU (gfx950); none is visible")
@@ -112,6 +113,8 @@ class Context:
         cfg.lr, cfg.beta1, cfg.beta2, cfg.eps = lr, beta1, beta2, eps
         cfg.tile_points = tile_points
         cfg.blocks_per_cu = blocks_per_cu
+        cfg.gemm_priority_off = 0 if gemm_priority else 1
+        cfg.ranges_per_wg = int(ranges_per_wg)
         cfg.max_query_points = max_query_points
         self.cfg = cfg
         arr = (PinnSubdomain * self.n_sub)()

@@ -317,6 +317,9 @@ static pinn_status validate(const pinn_config* cfg, const pinn_subdomain* subs) 
   if (cfg->tile_points != 0 && cfg->tile_points != 16 && cfg->tile_points != 32)
     return fail(PINN_E_INVAL, "tile_points must be 0, 16 or 32");
   if (cfg->blocks_per_cu < 0) return fail(PINN_E_INVAL, "blocks_per_cu must be >= 0");
+  if (cfg->gemm_priority_off != 0 && cfg->gemm_priority_off != 1)
+    return fail(PINN_E_INVAL, "gemm_priority_off must be 0 or 1");
+  if (cfg->ranges_per_wg < 0 || cfg->ranges_per_wg > 64) return fail(PINN_E_INVAL, "ranges_per_wg must be 0..64");
   if (cfg->max_query_points < 0 || cfg->max_query_points > (int64_t)INT32_MAX)
     return fail(PINN_E_INVAL, "max_query_points out of range");
   if (cfg->flags & ~PINN_GRAPH) return fail(PINN_E_INVAL, "unknown config flags 0x%x", cfg->flags);
@@ -432,10 +435,12 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   const int max_wg = c->num_cu * c->step_occ;
   c->n_wg = std::max(1, std::min(c->n_items, max_wg));
   // With several workgroups per compute unit the co-resident ones advance at
-  // different rates; ranges handed out in turn (four per workgroup) even it out.
+  // different rates; ranges handed out in turn (four per workgroup unless the
+  // caller's tuning says otherwise) even it out.
   c->dynamic = c->step_occ > 1;
+  const int rpw = cfg->ranges_per_wg > 0 ? cfg->ranges_per_wg : 4;
   auto ranges_for = [&](int n_items, int n_wg) {
-    return c->dynamic ? std::max(1, std::min(n_items, 4 * n_wg)) : n_wg;
+    return c->dynamic ? std::max(1, std::min(n_items, rpw * n_wg)) : n_wg;
   };
   c->n_ranges = ranges_for(c->n_items, c->n_wg);
   std::vector<int32_t> wg_begin;
@@ -609,6 +614,7 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   c->sargs.wg_begin = c->d_wg_begin;
   c->sargs.counter = c->dynamic ? c->d_counters : nullptr;
   c->sargs.n_ranges = c->n_ranges;
+  c->sargs.prio = cfg->gemm_priority_off ? 0 : 1;
   c->sargs.slabs = c->d_slabs;
   c->sargs.stash = c->d_stash;
   c->sargs.stash_per_wg = c->stash_per_wg;

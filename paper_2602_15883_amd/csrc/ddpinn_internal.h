@@ -95,6 +95,8 @@ struct StepArgs {
   int64_t stash_per_wg;     // floats
   float nu;
   int32_t lds_floats;
+  int32_t prio;             // the younger half of the waves raises its priority for its GEMMs
+  int32_t pad_;
 };
 
 struct ReduceArgs {

@@ -111,6 +111,19 @@ __device__ __forceinline__ void act_d2(float z, float& s, float& s1, float& s2) 
   }
 }
 
+// SV: the argument is tanh(z0) itself (kept in the stash in place of z0);
+// tanh's derivatives are polynomials in it, so tanh is not evaluated again
+template <int ACT, bool SV>
+__device__ __forceinline__ void act_d2s(float v, float& s, float& s1, float& s2) {
+  if constexpr (SV && ACT == ACT_TANH) {
+    s = v;
+    s1 = 1.f - s * s;
+    s2 = -2.f * s * s1;
+  } else {
+    act_d2<ACT>(v, s, s1, s2);
+  }
+}
+
 template <int ACT>
 __device__ __forceinline__ void act_d3(float z, float& s, float& s1, float& s2, float& s3) {
   if constexpr (ACT == ACT_SIN) {
@@ -122,6 +135,18 @@ __device__ __forceinline__ void act_d3(float z, float& s, float& s1, float& s2, 
     s1 = 1.f - s * s;
     s2 = -2.f * s * s1;
     s3 = 2.f * s1 * (3.f * s * s - 1.f);
+  }
+}
+
+template <int ACT, bool SV>
+__device__ __forceinline__ void act_d3s(float v, float& s, float& s1, float& s2, float& s3) {
+  if constexpr (SV && ACT == ACT_TANH) {
+    s = v;
+    s1 = 1.f - s * s;
+    s2 = -2.f * s * s1;
+    s3 = 2.f * s1 * (3.f * s * s - 1.f);
+  } else {
+    act_d3<ACT>(v, s, s1, s2, s3);
   }
 }
 
@@ -204,7 +229,7 @@ __device__ __forceinline__ void act_store_bwd(float* buf, int S2, const v4f (&z)
 //   zbar_j  = s1 hbar_j + 2 s2 z_j hbar_jj      (spatial j; time: s1 hbar_t)
 //   zbar_0  = s1 hbar_0 + s2 sum_j z_j hbar_j + sum_j (s3 z_j^2 + s2 z_jj) hbar_jj
 //   with s1, s2, s3 the first three derivatives of the activation at z_0
-template <int DIM, int NCB, int MODE, int ACT>
+template <int DIM, int NCB, int MODE, int ACT, bool SV = false>
 __device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]) {
   using M = ModeCfg<DIM, NCB, MODE>;
   constexpr int NPB = M::NPB;
@@ -214,7 +239,7 @@ __device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]
     for (int i = 0; i < 4; ++i) {
       if constexpr (MODE == M_PDE) {
         float s, s1, s2, s3;
-        act_d3<ACT>(zs[pb][i], s, s1, s2, s3);
+        act_d3s<ACT, SV>(zs[pb][i], s, s1, s2, s3);
         float z0b = s1 * hb[pb][i];
 #pragma unroll
         for (int jj = 0; jj <= DIM; ++jj) {
@@ -235,7 +260,7 @@ __device__ __forceinline__ void act_adjoint(v4f (&hb)[NCB], const v4f (&zs)[NCB]
         hb[pb][i] = z0b;
       } else {
         float s, s1, s2;
-        act_d2<ACT>(zs[pb][i], s, s1, s2);
+        act_d2s<ACT, SV>(zs[pb][i], s, s1, s2);
         hb[pb][i] *= s1;
       }
     }
@@ -291,7 +316,9 @@ __device__ __forceinline__ void mfma_tail(const v4f a, const float* bb, int S, i
 }
 
 // K = 4*K4 + KT steps: K4 full chunks of four, then KT (0..3) more
-template <int NCB, bool TR = false>
+// INIT: acc is written, not accumulated into: the first MFMA of each
+// accumulator takes 0 as its C operand (no zeroing of the accumulators)
+template <int NCB, bool TR = false, bool INIT = false>
 __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const float* bufB,
                                           int S, int K4, int g, int j, int lane,
                                           v4f (&acc)[NCB], int KT) {
@@ -302,6 +329,29 @@ __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const
   // flight while the MFMAs of the current one run
   v4f a0 = ldg4u(afrag, lo);
   int s4 = 0;
+  if constexpr (INIT) {
+    v4f b[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const v4f*>(bb + cb * 16 * S);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma_or<TR>(a0[0], b[cb][0], zero4());
+    const int q1 = K4 > 0 ? 4 : KT;   // K-steps of the first chunk
+    if (q1 > 1) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma_or<TR>(a0[1], b[cb][1], acc[cb]);
+    }
+    if (q1 > 2) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma_or<TR>(a0[2], b[cb][2], acc[cb]);
+    }
+    if (q1 > 3) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma_or<TR>(a0[3], b[cb][3], acc[cb]);
+    }
+    if (K4 == 0) return;
+    s4 = 1;
+    a0 = ldg4u(afrag + (KC > 1 ? 1 : 0) * 256, lo);
+  }
   for (; s4 + 2 <= K4; s4 += 2) {
     const v4f a1 = ldg4u(afrag + (s4 + 1) * 256, lo);
     mfma_step<NCB, TR>(a0, bb, S, s4, acc);
@@ -425,7 +475,7 @@ __device__ __forceinline__ void store_fwd_t(float* buf, int S, const v4f (&a)[NC
 
 // h = act(z) of a stashed (transposed) pre-activation stack, written into the
 // neuron-major LDS layout [neuron][col] (stride S2): four columns per store
-template <int DIM, int NCB, int MODE, int ACT>
+template <int DIM, int NCB, int MODE, int ACT, bool SV = false>
 __device__ __forceinline__ void act_store_bwd_t(float* buf, int S2, const v4f (&z)[NCB], int w, int g, int j) {
   using M = ModeCfg<DIM, NCB, MODE>;
   constexpr int NPB = M::NPB;
@@ -438,7 +488,7 @@ __device__ __forceinline__ void act_store_bwd_t(float* buf, int S2, const v4f (&
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       float a0, a1, a2;
-      act_d2<ACT>(z[pb][i], a0, a1, a2);
+      act_d2s<ACT, SV>(z[pb][i], a0, a1, a2);
       sv[i] = a0;
       s1[i] = a1;
       s2[i] = a2;
@@ -457,7 +507,8 @@ __device__ __forceinline__ void act_store_bwd_t(float* buf, int S2, const v4f (&
   }
 }
 
-// dw[t] += Zbar(this wave's neurons, registers) * Hprev[16(nb0+t) + n][.]^T
+// dw[t] = Zbar(this wave's neurons, registers) * Hprev[16(nb0+t) + n][.]^T,
+// t < NNB (the first MFMA takes 0 as its C operand)
 //   Hprev from bufHb ([neuron][col], stride S2); K = the tile's columns
 template <int NCB, int NNB>
 __device__ __forceinline__ void gemm_dw_t(const v4f (&zb)[NCB], const float* bufHb, int S2, int g, int j,
@@ -471,7 +522,7 @@ __device__ __forceinline__ void gemm_dw_t(const v4f (&zb)[NCB], const float* buf
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int t = 0; t < NNB; ++t) dw[t] = mfma4(zb[cb][i], b[t][i], dw[t]);
+      for (int t = 0; t < NNB; ++t) dw[t] = mfma4(zb[cb][i], b[t][i], (cb == 0 && i == 0) ? zero4() : dw[t]);
   }
 }
 
@@ -820,6 +871,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   const size_t stash_rb = (size_t)NWV * H * NCB * 256;
   const uint32_t lo16 = (uint32_t)lane * 16u;   // this lane's byte offset in a 1 KiB wave fragment
   const float nu = args.nu;
+  const bool prio = args.prio != 0;   // raise the younger waves' priority for their GEMMs
+  constexpr bool SV = ACT == ACT_TANH;  // one-row-block kernels: the stash keeps tanh(z0)
 
   // segment accumulators; dW_{H+1} entry tid + r*nthr is thread tid's
   float lacc[6];
@@ -898,32 +951,40 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
     float* hin = bufH;
     float* hout = bufG;
     if constexpr (RPW == 1) {
+      // The stash keeps each layer's pre-activation stack for the adjoint;
+      // with tanh its value channel keeps tanh(z0) instead of z0 (the
+      // adjoint needs z0 only through tanh and its derivatives, which are
+      // polynomials in tanh), so the backward does not evaluate tanh again.
+      const int nvb = pde ? MP::NPB : MV::NPB;   // value-channel column blocks
+      auto stash_layer = [&](int li, bool value_blocks) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          if ((cb < nvb) == value_blocks || !SV) stg4u(stash_w + (li * NCB + cb) * 256, lo16, acc[cb]);
+      };
       if (pde) input_layer_t<DIM, NCB, M_PDE>(acc, W1p, bp, xin, w, g, j);
       else input_layer_t<DIM, NCB, M_VALUE>(acc, W1p, bp, xin, w, g, j);
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + (0 * NCB + cb) * 256, lo16, acc[cb]);
+      stash_layer(0, false);
       if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
       else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
+      if constexpr (SV) stash_layer(0, true);
       store_fwd_t<NCB>(hin, S, acc, w, g, j);
       __syncthreads();
 
       // ---- forward: hidden layers 2..H
       for (int l = 2; l <= H; ++l) {
         const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)w * 16 * Wp;
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
         // The two waves sharing a SIMD run the same GEMM; the hardware favours
         // the older one, which then idles at the next barrier while the younger
         // finishes.  Raising the younger half's priority for the GEMM evens them.
-        if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-        gemm_rows<NCB, true>(Wf, hin, S, K4, g, j, lane, acc, KT);
+        if (prio && w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
+        gemm_rows<NCB, true, true>(Wf, hin, S, K4, g, j, lane, acc, KT);
         __builtin_amdgcn_s_setprio(0);
         if (pde) add_bias_t<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, j);
         else add_bias_t<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, j);
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16, acc[cb]);
+        stash_layer(l - 1, false);
         if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
         else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
+        if constexpr (SV) stash_layer(l - 1, true);
         store_fwd_t<NCB>(hout, S, acc, w, g, j);
         __syncthreads();
         float* t = hin;
@@ -954,7 +1015,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)rb * 16 * Wp;
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
-          if (w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
+          if (prio && w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
           gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc, KT);
           __builtin_amdgcn_s_setprio(0);
           if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, rb, g);
@@ -995,7 +1056,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)rb * 16 * Wp;
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
-          if (w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
+          if (prio && w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
           gemm_rows<NCB>(Wf, hin, S, K4, g, j, lane, acc, KT);
           __builtin_amdgcn_s_setprio(0);
           if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, rb, g);
@@ -1147,8 +1208,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
 
       // ---- hidden and input layer adjoints (transposed tiles)
       for (int l = H; l >= 1; --l) {
-        if (pde) act_adjoint<DIM, NCB, M_PDE, ACT>(acc, zs);
-        else act_adjoint<DIM, NCB, M_VALUE, ACT>(acc, zs);
+        if (pde) act_adjoint<DIM, NCB, M_PDE, ACT, SV>(acc, zs);
+        else act_adjoint<DIM, NCB, M_VALUE, ACT, SV>(acc, zs);
         // db_l: value-channel columns of this lane's neuron
         {
           const int npb = pde ? MP::NPB : MV::NPB;
@@ -1200,8 +1261,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         __syncthreads();
         store_fwd_t<NCB>(bufG, S, acc, w, g, j);
         // recompute h_{l-1} from z_{l-1}
-        if (pde) act_store_bwd_t<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w, g, j);
-        else act_store_bwd_t<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w, g, j);
+        if (pde) act_store_bwd_t<DIM, NCB, M_PDE, ACT, SV>(bufH, S2, zs, w, g, j);
+        else act_store_bwd_t<DIM, NCB, M_VALUE, ACT, SV>(bufH, S2, zs, w, g, j);
         __syncthreads();
         // dW_l += Zbar_l H_{l-1}^T into this segment's slab, Zbar_l from the
         // registers (at most 8 column blocks: widths up to 128); the slab's
@@ -1209,7 +1270,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         {
           float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
           const bool first = item.flags & ITEM_FIRST;
-          if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);   // as in the forward GEMM
+          if (prio && w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);   // as in the forward GEMM
           // the current slab values of both groups are requested up front
           v4f old8[8];
 #pragma unroll
@@ -1235,11 +1296,9 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         __builtin_amdgcn_s_setprio(0);
         // Hbar_{l-1} = W_l^T Zbar_l
         {
-#pragma unroll
-          for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
           const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
-          if (w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-          gemm_rows<NCB, true>(WT, bufG, S, K4, g, j, lane, acc, KT);
+          if (prio && w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
+          gemm_rows<NCB, true, true>(WT, bufG, S, K4, g, j, lane, acc, KT);
           __builtin_amdgcn_s_setprio(0);
         }
       }
@@ -1270,7 +1329,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           dbo += s;
         }
       }
-      const bool raise = w >= (NWV >> 1);   // wave priority for the GEMMs, as in the forward
+      const bool raise = prio && w >= (NWV >> 1);   // wave priority for the GEMMs, as in the forward
       for (int r = 0; r < nrb; ++r) {
         const int rb = w + r * NWV;
         float* st = stash_w + r * stash_rb;

@@ -1,13 +1,16 @@
 """Autotuner for the fused step's launch shape.
 
 Knobs: collocation points per tile (16, or 32 when the workgroup has at most
-four waves) and persistent workgroups per compute unit.  Each candidate is a
-fresh context over the same device tensors; its fused-kernel time is measured
-with HIP events (PINN_TIME_KERNEL) over a few steps without the Adam update.
-Winners are cached in JSON keyed by (arch, dim, width, depth, subdomain
-count, log2 of the collocation point count, activation).  Candidates that the
-library maps to the same launch (points per tile, workgroup count) are timed
-once.  Lookup order: the user cache
+four waves), persistent workgroups per compute unit, whether the younger half
+of a workgroup's waves raises its priority for its GEMMs, and how many item
+ranges each workgroup takes in turn when several share a compute unit.  Each
+candidate is a fresh context over the same device tensors; its fused-kernel
+time is measured with HIP events tied to the kernel's dispatch
+(PINN_TIME_KERNEL) over a few steps without the Adam update.  Winners are
+cached in JSON keyed by (arch, dim, width, depth, subdomain count, log2 of
+the collocation point count, activation).  Candidates that the library maps
+to the same launch (points per tile, workgroup count, priority, ranges) are
+timed once.  Lookup order: the user cache
 (DDPINN_TUNE_CACHE or ~/.cache/ddpinn/tune.json), then the table shipped with
 the package (tuned.json), else the library defaults.
 """
@@ -74,14 +77,36 @@ def store(key: str, entry: dict, path: Optional[str] = None):
     os.replace(tmp, path)
 
 
+def ctx_cu_count() -> int:
+    try:
+        return int(torch.cuda.get_device_properties(0).multi_processor_count)
+    except Exception:
+        return 0
+
+
+def shape_of(entry: dict) -> dict:
+    """The launch-shape keyword arguments of a tuning-table entry (entries
+    from before the priority and range knobs default to the library's)."""
+    return {"tile_points": int(entry["tile_points"]), "blocks_per_cu": int(entry["blocks_per_cu"]),
+            "gemm_priority": bool(entry.get("gemm_priority", True)),
+            "ranges_per_wg": int(entry.get("ranges_per_wg", 0))}
+
+
 def candidates(width: int) -> List[dict]:
+    """Launch shapes: collocation points per tile (32 only up to four waves),
+    persistent workgroups per compute unit, the GEMM wave priority, and the
+    item ranges each workgroup takes in turn when several share a compute
+    unit (one workgroup per compute unit takes one range)."""
     waves = (width + 15) // 16
     out = []
     for tp in (16, 32):
         if tp == 32 and waves > 4:
             continue
         for bpc in (1, 2, 3, 4):
-            out.append({"tile_points": tp, "blocks_per_cu": bpc})
+            for prio in (True, False):
+                for rpw in ((0,) if bpc == 1 else (2, 4, 8)):
+                    out.append({"tile_points": tp, "blocks_per_cu": bpc, "gemm_priority": prio,
+                                "ranges_per_wg": rpw})
     return out
 
 
@@ -94,7 +119,8 @@ def measure(make_ctx, cand: dict, steps: int = 3, warmup: int = 1, seen: Optiona
         info = ctx.launch_info()
         if info["tile_points"] != cand["tile_points"]:
             return float("inf")
-        launch = (info["tile_points"], info["n_wg"])
+        launch = (info["tile_points"], info["n_wg"], bool(cand.get("gemm_priority", True)),
+                  int(cand.get("ranges_per_wg", 0)) if info["n_wg"] > ctx_cu_count() else 0)
         if seen is not None and launch in seen:
             return seen[launch]
         for _ in range(warmup):
@@ -114,7 +140,8 @@ def measure(make_ctx, cand: dict, steps: int = 3, warmup: int = 1, seen: Optiona
 def autotune(make_ctx, dim, width, depth, n_sub, n_pde, steps: int = 3,
              cache: bool = True, force: bool = False, verbose: bool = False,
              path: Optional[str] = None, activation: str = "tanh") -> dict:
-    """Return the best {tile_points, blocks_per_cu} for this shape, from the
+    """Return the best launch shape {tile_points, blocks_per_cu,
+    gemm_priority, ranges_per_wg} for this network and problem size, from the
     caches or by timing every candidate.  make_ctx(**cand) builds a Context.
     With cache, the winner and every trial are stored in `path` (default: the
     user cache)."""
@@ -122,7 +149,7 @@ def autotune(make_ctx, dim, width, depth, n_sub, n_pde, steps: int = 3,
     if not force:
         e = lookup(key)
         if e:
-            return {"tile_points": e["tile_points"], "blocks_per_cu": e["blocks_per_cu"]}
+            return shape_of(e)
     best, best_ms, trials = None, float("inf"), []
     seen: dict = {}
     cands = candidates(width)
