@@ -367,6 +367,25 @@ __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const
   if (KT) mfma_tail<NCB, TR>(a0, bb, S, s4, KT, acc);
 }
 
+// acc = the rows of one row block over the K chunks [c0, c1) of the KC
+// chunks of a lane group's segment (the last chunk holds KT steps if KT > 0):
+// one part of a GEMM whose K range is split between waves
+template <int NCB>
+__device__ __forceinline__ void gemm_rows_part(const float* __restrict__ afrag, const float* bufB, int S, int KC,
+                                               int KT, int c0, int c1, int g, int j, int lane, v4f (&acc)[NCB]) {
+  const float* bb = bufB + j * S + g * (4 * KC);
+  const uint32_t lo = (uint32_t)lane * 16u;
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
+  v4f a = ldg4u(afrag + c0 * 256, lo);
+  for (int c = c0; c < c1; ++c) {
+    const v4f an = (c + 1 < c1) ? ldg4u(afrag + (c + 1) * 256, lo) : a;
+    if (c == KC - 1 && KT) mfma_tail<NCB>(a, bb, S, c, KT, acc);
+    else mfma_step<NCB>(a, bb, S, c, acc);
+    a = an;
+  }
+}
+
 // dw[t] += sum_col Zbar[16w + m][col] * Hprev[16(nb0+t) + n][col], t < NNB
 //   Zbar from bufG ([col][neuron], stride S); Hprev from bufHb ([neuron][col], stride S2)
 //   Column of step (s4, q) in lane group g: 16*s4 + 4*g + q.  The four groups
@@ -631,8 +650,21 @@ __device__ __forceinline__ void residuals(F Y, float nu, float (&r)[DIM + 1]) {
 // ---------------------------------------------------------------------------
 struct StepLds {
   int S, S2, NCOL;
-  int bufH, bufG, ys, yb, xin, acc1, dbacc, red, sched, total;
+  int bufH, bufG, ys, yb, xin, acc1, dbacc, red, sched, part, nparts, total;
 };
+
+// Row blocks beyond the eight waves.  With exactly two of them (Wp = 160, the
+// paper's 6x150 network) the plan with two stacks per tile splits their
+// GEMMs' K range in halves between four waves, one per SIMD, so no wave
+// carries more than 1.5 row blocks (instead of 2, 2, 1, ...) and every SIMD
+// 2.5 (instead of 3, 3, 2, 2).  The parts meet in four LDS tiles; only where
+// those fit in the 160 KB of LDS as well.
+constexpr int kLdsBytes = 160 * 1024;
+__host__ __device__ inline int step_ksplit_parts(int Wp, int split, int floats_before, int NCB) {
+  const int nw = Wp / 16, ne = nw - (nw < 8 ? nw : 8);
+  const bool want = !split && ne == 2;
+  return (want && (floats_before + 4 * NCB * 256) * 4 <= kLdsBytes) ? 4 : 0;
+}
 
 // Row stride of the [col][neuron] stacks.  Up to 128 neurons it is a
 // compile-time constant per kernel instance (68, 100 or 132 floats, the
@@ -661,6 +693,9 @@ __host__ __device__ inline StepLds step_lds(int D, int Wp, int H, int NCB, int S
   L.dbacc = o; o += (H * Wp + 3) & ~3;
   L.red = o;  o += 64;
   L.sched = o; o += 4;   // the item range taken by the workgroup
+  L.part = o;
+  L.nparts = step_ksplit_parts(Wp, 0, o, NCB);
+  o += L.nparts * NCB * 256;
   L.total = o;
   return L;
 }
@@ -688,6 +723,9 @@ __host__ __device__ inline StepLds step_lds_split(int D, int Wp, int H, int NCB,
   L.dbacc = o; o += (H * Wp + 3) & ~3;
   L.red = o;  o += 64;
   L.sched = o; o += 4;
+  L.part = o;
+  L.nparts = step_ksplit_parts(Wp, 1, o, NCB);
+  o += L.nparts * NCB * 256;
   L.total = o;
   return L;
 }
@@ -861,7 +899,13 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   float* acc1 = lds + L.acc1;
   float* dbacc = lds + L.dbacc;
   float* red = lds + L.red;
+  float* part = lds + L.part;
   const int S = SS ? SS : L.S, S2 = L.S2;
+  // two row blocks beyond the eight waves (one-stack plan): their GEMMs are
+  // split over K between waves w and w + 2 (w < 2, the blocks' owners), and
+  // summed by the owner from four LDS tiles
+  const bool ks = RPW == 2 && !SPLIT && L.nparts == 4;
+  const int KCh = ((sh.Kq + 3) >> 2);   // K chunks of a lane group's segment
 
   // row blocks of this wave: w, and w + NWV when there are more than NWV
   const int nrb = (RPW == 1) ? 1 : (w + NWV < NW ? 2 : 1);
@@ -1009,10 +1053,11 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       }
       __syncthreads();
       for (int l = 2; l <= H; ++l) {
+        const float* Wl = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp;
         for (int r = 0; r < nrb; ++r) {
           const int rb = w + r * NWV;
           float* st = stash_w + r * stash_rb;
-          const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)rb * 16 * Wp;
+          const float* Wf = Wl + (size_t)rb * 16 * Wp;
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
           if (prio && w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
@@ -1050,10 +1095,11 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       }
       __syncthreads();
       for (int l = 2; l <= H; ++l) {
-        for (int r = 0; r < nrb; ++r) {
+        const float* Wl = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp;
+        for (int r = 0; r < (ks ? 1 : nrb); ++r) {
           const int rb = w + r * NWV;
           float* st = stash_w + r * stash_rb;
-          const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)rb * 16 * Wp;
+          const float* Wf = Wl + (size_t)rb * 16 * Wp;
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
           if (prio && w >= (NWV >> 1)) __builtin_amdgcn_s_setprio(2);
@@ -1066,6 +1112,31 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
           else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
           store_fwd<NCB>(hout, S, acc, rb, g, j);
+        }
+        if (ks) {
+          // the two extra row blocks: half of the K range each for waves
+          // 0..3 (block NWV + (w & 1), half w >> 1), summed by the owner
+          if (w < 4) {
+            const int e = NWV + (w & 1), c0 = (w >> 1) ? KCh / 2 : 0, c1 = (w >> 1) ? KCh : KCh / 2;
+            gemm_rows_part<NCB>(Wl + (size_t)e * 16 * Wp, hin, S, KCh, KT, c0, c1, g, j, lane, acc);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) *reinterpret_cast<v4f*>(part + (w * NCB + cb) * 256 + lane * 4) = acc[cb];
+          }
+          __syncthreads();
+          if (nrb == 2) {
+            const int e = w + NWV;
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              acc[cb] = *reinterpret_cast<const v4f*>(part + (w * NCB + cb) * 256 + lane * 4) +
+                        *reinterpret_cast<const v4f*>(part + ((w + 2) * NCB + cb) * 256 + lane * 4);
+            if (pde) add_bias<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, e, g);
+            else add_bias<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, e, g);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) stg4u(stash_w + stash_rb + ((l - 1) * NCB + cb) * 256, lo16, acc[cb]);
+            if (pde) act_forward<DIM, NCB, M_PDE, ACT>(acc);
+            else act_forward<DIM, NCB, M_VALUE, ACT>(acc);
+            store_fwd<NCB>(hout, S, acc, e, g, j);
+          }
         }
         __syncthreads();
         float* t = hin;
@@ -1381,11 +1452,12 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
             dw_tiles<NCBH>(sw, (item.flags & ITEM_FIRST) && hh == 0, bufG, S, bufH, S2, NW,
                            w * NW * NW / NWV, (w + 1) * NW * NW / NWV, g, j, lo16);
             // Hbar_{l-1} of this half into the stash slot of Zbar_l (consumed)
+            const float* WTl = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp;
             for (int r = 0; r < nrb; ++r) {
               const int rb = w + r * NWV;
 #pragma unroll
               for (int c = 0; c < NCBH; ++c) t[c] = zero4();
-              const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)rb * 16 * Wp;
+              const float* WT = WTl + (size_t)rb * 16 * Wp;
               gemm_rows<NCBH>(WT, bufG, S, K4, g, j, lane, t, KT);
               float* st = stash_w + r * stash_rb + zl + (size_t)hh * NCBH * 256;
 #pragma unroll
@@ -1435,14 +1507,24 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
                         w * NW * NW / NWV, (w + 1) * NW * NW / NWV, g, j, lo16);
           __builtin_amdgcn_s_setprio(0);
           // Hbar_{l-1} = W_l^T Zbar_l, then the adjoint of layer l-1, per block
-          for (int r = 0; r < nrb; ++r) {
+          const float* WTl = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp;
+          if (ks && w < 4) {
+            // the extra row blocks' Hbar over half of the K range (as in the forward)
+            const int e = NWV + (w & 1), c0 = (w >> 1) ? KCh / 2 : 0, c1 = (w >> 1) ? KCh : KCh / 2;
+            if (raise) __builtin_amdgcn_s_setprio(2);
+            gemm_rows_part<NCB>(WTl + (size_t)e * 16 * Wp, bufG, S, KCh, KT, c0, c1, g, j, lane, acc);
+            __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) *reinterpret_cast<v4f*>(part + (w * NCB + cb) * 256 + lane * 4) = acc[cb];
+          }
+          for (int r = 0; r < (ks ? 1 : nrb); ++r) {
             const int rb = w + r * NWV;
             float* st = stash_w + r * stash_rb;
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(st + ((l - 2) * NCB + cb) * 256, lo16);
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) acc[cb] = zero4();
-            const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)rb * 16 * Wp;
+            const float* WT = WTl + (size_t)rb * 16 * Wp;
             if (raise) __builtin_amdgcn_s_setprio(2);
             gemm_rows<NCB>(WT, bufG, S, K4, g, j, lane, acc, KT);
             __builtin_amdgcn_s_setprio(0);
@@ -1451,6 +1533,20 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
             if (l > 2 && r + 1 < nrb) {
 #pragma unroll
               for (int cb = 0; cb < NCB; ++cb) stg4u(st + ((l - 2) * NCB + cb) * 256, lo16, acc[cb]);
+            }
+          }
+          if (ks) {
+            __syncthreads();   // the halves are in LDS
+            if (nrb == 2) {
+              const int e = w + NWV;
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(stash_w + stash_rb + ((l - 2) * NCB + cb) * 256, lo16);
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb)
+                acc[cb] = *reinterpret_cast<const v4f*>(part + (w * NCB + cb) * 256 + lane * 4) +
+                          *reinterpret_cast<const v4f*>(part + ((w + 2) * NCB + cb) * 256 + lane * 4);
+              if (pde) adjoint_rows<DIM, NCB, M_PDE, ACT>(acc, zs, dbacc, acc1, xin, Wp, e, l - 1, g, j);
+              else adjoint_rows<DIM, NCB, M_VALUE, ACT>(acc, zs, dbacc, acc1, xin, Wp, e, l - 1, g, j);
             }
           }
         }
