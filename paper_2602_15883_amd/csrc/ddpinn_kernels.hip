@@ -841,19 +841,39 @@ __device__ __forceinline__ void act_store_bwd_cols(float* buf, int S2, const v4f
 // H rows of its column block), so any wave can take any tile: the NW*NW tiles
 // are cut into equal contiguous runs, one per wave, which balances the SIMDs
 // whatever row blocks their waves own (one writer per slab float still).
-// Up to four tiles of one row block share the A operand; the old slab values
-// are requested before each group's GEMM so the read overlaps it.
+// Up to four tiles of one row block share the A operand.  The old slab values
+// of a group are requested one group ahead (during the previous group's
+// GEMM), so two groups' GEMMs cover the read's latency.
 template <int NCB>
 __device__ __forceinline__ void dw_tiles(float* sw, bool first, const float* bufG, int S, const float* bufH, int S2,
                                          int NW, int t0, int t1, int g, int j, uint32_t lo16) {
-  for (int t = t0; t < t1;) {
-    const int rb = t / NW, nb0 = t - rb * NW;
-    int nnb = NW - nb0 < 4 ? NW - nb0 : 4;
-    if (nnb > t1 - t) nnb = t1 - t;
-    v4f old[4];
+  auto group = [&](int t, int& rb, int& nb0) {
+    rb = t / NW;
+    nb0 = t - rb * NW;
+    const int n = NW - nb0 < 4 ? NW - nb0 : 4;
+    return n < t1 - t ? n : t1 - t;
+  };
+  v4f oldn[4];
+  if (t0 < t1) {
+    int rb, nb0;
+    const int nnb = group(t0, rb, nb0);
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-      old[q] = (q < nnb && !first) ? ldg4u(sw + (size_t)(rb * NW + nb0 + q) * 256, lo16) : zero4();
+      oldn[q] = (q < nnb && !first) ? ldg4u(sw + (size_t)(rb * NW + nb0 + q) * 256, lo16) : zero4();
+  }
+  for (int t = t0; t < t1;) {
+    int rb, nb0;
+    const int nnb = group(t, rb, nb0);
+    v4f old[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) old[q] = oldn[q];
+    if (t + nnb < t1 && !first) {
+      int rb2, nb2;
+      const int n2 = group(t + nnb, rb2, nb2);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        oldn[q] = q < n2 ? ldg4u(sw + (size_t)(rb2 * NW + nb2 + q) * 256, lo16) : zero4();
+    }
     v4f dw[4] = {zero4(), zero4(), zero4(), zero4()};
     switch (nnb) {
       case 4: gemm_dw<NCB, 4>(bufG, S, bufH, S2, rb, g, j, nb0, dw); break;
