@@ -926,6 +926,19 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   // summed by the owner from four LDS tiles
   const bool ks = RPW == 2 && !SPLIT && L.nparts == 4;
   const int KCh = ((sh.Kq + 3) >> 2);   // K chunks of a lane group's segment
+  // dW tiles of this wave (two-row-block kernels): the layer's NW*NW tiles in
+  // contiguous runs whose lengths even out each wave's MFMA work between two
+  // barriers.  A row block of Hbar costs NW dW tiles in multiply-adds (both
+  // run over the same columns), so a wave with fewer Hbar row blocks takes
+  // more dW tiles: wave v's share is (2 NW^2 - NWV * NW * rows(v)) / NWV,
+  // rows(v) its Hbar row blocks (1.5 for waves 0..3 with the K-split above).
+  // cut(v) is the sum of the shares of waves < v, in half row blocks.
+  auto dw_cut = [&](int v) {
+    const int ne = NW - NWV;
+    const int hb = ks ? 3 * (v < 4 ? v : 4) + 2 * (v > 4 ? v - 4 : 0) : 2 * v + 2 * (v < ne ? v : ne);
+    return (4 * NW * NW * v - NW * NWV * hb) / (2 * NWV);
+  };
+  const int dw_t0 = (RPW == 2) ? dw_cut(w) : 0, dw_t1 = (RPW == 2) ? dw_cut(w + 1) : 0;
 
   // row blocks of this wave: w, and w + NWV when there are more than NWV
   const int nrb = (RPW == 1) ? 1 : (w + NWV < NW ? 2 : 1);
@@ -1469,8 +1482,8 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
             }
             __syncthreads();
             if (raise) __builtin_amdgcn_s_setprio(2);
-            dw_tiles<NCBH>(sw, (item.flags & ITEM_FIRST) && hh == 0, bufG, S, bufH, S2, NW,
-                           w * NW * NW / NWV, (w + 1) * NW * NW / NWV, g, j, lo16);
+            dw_tiles<NCBH>(sw, (item.flags & ITEM_FIRST) && hh == 0, bufG, S, bufH, S2, NW, dw_t0, dw_t1, g, j,
+                           lo16);
             // Hbar_{l-1} of this half into the stash slot of Zbar_l (consumed)
             const float* WTl = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp;
             for (int r = 0; r < nrb; ++r) {
@@ -1523,8 +1536,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           __syncthreads();
           float* sw = args.slabs + (size_t)item.slab * sh.slab_floats + sh.s_hid + (size_t)(l - 2) * Wp * Wp;
           if (raise) __builtin_amdgcn_s_setprio(2);
-          dw_tiles<NCB>(sw, item.flags & ITEM_FIRST, bufG, S, bufH, S2, NW,
-                        w * NW * NW / NWV, (w + 1) * NW * NW / NWV, g, j, lo16);
+          dw_tiles<NCB>(sw, item.flags & ITEM_FIRST, bufG, S, bufH, S2, NW, dw_t0, dw_t1, g, j, lo16);
           __builtin_amdgcn_s_setprio(0);
           // Hbar_{l-1} = W_l^T Zbar_l, then the adjoint of layer l-1, per block
           const float* WTl = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp;
