@@ -927,16 +927,18 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   const bool ks = RPW == 2 && !SPLIT && L.nparts == 4;
   const int KCh = ((sh.Kq + 3) >> 2);   // K chunks of a lane group's segment
   // dW tiles of this wave (two-row-block kernels): the layer's NW*NW tiles in
-  // contiguous runs whose lengths even out each wave's MFMA work between two
+  // contiguous runs whose lengths even out each wave's work between two
   // barriers.  A row block of Hbar costs NW dW tiles in multiply-adds (both
-  // run over the same columns), so a wave with fewer Hbar row blocks takes
-  // more dW tiles: wave v's share is (2 NW^2 - NWV * NW * rows(v)) / NWV,
-  // rows(v) its Hbar row blocks (1.5 for waves 0..3 with the K-split above).
-  // cut(v) is the sum of the shares of waves < v, in half row blocks.
+  // run over the same columns), and its share of the per-row-block VALU work
+  // around the GEMMs (recomputing h, the adjoint) adds about a quarter of
+  // that; so a wave with fewer Hbar row blocks takes more dW tiles: wave v's
+  // share is (9/4 NW^2 - 5/4 NWV * NW * rows(v)) / NWV, rows(v) its row
+  // blocks (1.5 for waves 0..3 with the K-split above).  cut(v) is the sum
+  // of the shares of waves < v, with rows counted in halves.
   auto dw_cut = [&](int v) {
     const int ne = NW - NWV;
     const int hb = ks ? 3 * (v < 4 ? v : 4) + 2 * (v > 4 ? v - 4 : 0) : 2 * v + 2 * (v < ne ? v : ne);
-    return (4 * NW * NW * v - NW * NWV * hb) / (2 * NWV);
+    return (18 * NW * NW * v - 5 * NW * NWV * hb) / (8 * NWV);
   };
   const int dw_t0 = (RPW == 2) ? dw_cut(w) : 0, dw_t1 = (RPW == 2) ? dw_cut(w + 1) : 0;
 
