@@ -318,16 +318,21 @@ __device__ __forceinline__ void mfma_tail(const v4f a, const float* bb, int S, i
 // K = 4*K4 + KT steps: K4 full chunks of four, then KT (0..3) more
 // INIT: acc is written, not accumulated into: the first MFMA of each
 // accumulator takes 0 as its C operand (no zeroing of the accumulators)
-template <int NCB, bool TR = false, bool INIT = false>
+template <int NCB, bool TR = false, bool INIT = false, bool DEEP = false>
 __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const float* bufB,
                                           int S, int K4, int g, int j, int lane,
                                           v4f (&acc)[NCB], int KT) {
   const int KC = K4 + (KT ? 1 : 0);   // chunks per row block (4*KC = Wp/4, a lane group's segment)
   const float* bb = bufB + j * S + g * (4 * KC);
   const uint32_t lo = (uint32_t)lane * 16u;
-  // two weight-fragment registers: the fragment of the next chunk is in
-  // flight while the MFMAs of the current one run
-  v4f a0 = ldg4u(afrag, lo);
+  // DEEP: three weight-fragment registers, the fragments of the next two
+  // chunks are in flight while the MFMAs of the current one run (one chunk's
+  // MFMAs do not always cover the latency of a fragment read from L2);
+  // otherwise two (for kernels without the four registers to spare).
+  // Chunks past the last re-read the last one.
+  auto frag = [&](int c) { return ldg4u(afrag + (c < KC ? c : KC - 1) * 256, lo); };
+  v4f a0 = frag(0);
+  v4f a1 = frag(1);
   int s4 = 0;
   if constexpr (INIT) {
     v4f b[NCB];
@@ -350,16 +355,42 @@ __device__ __forceinline__ void gemm_rows(const float* __restrict__ afrag, const
     }
     if (K4 == 0) return;
     s4 = 1;
-    a0 = ldg4u(afrag + (KC > 1 ? 1 : 0) * 256, lo);
+    a0 = a1;
+    a1 = frag(2);
   }
-  for (; s4 + 2 <= K4; s4 += 2) {
-    const v4f a1 = ldg4u(afrag + (s4 + 1) * 256, lo);
+  if constexpr (!DEEP) {
+    // a0, a1: the fragments of chunks s4 and s4 + 1
+    for (; s4 + 2 <= K4; s4 += 2) {
+      mfma_step<NCB, TR>(a0, bb, S, s4, acc);
+      a0 = frag(s4 + 2);
+      mfma_step<NCB, TR>(a1, bb, S, s4 + 1, acc);
+      a1 = frag(s4 + 3);
+    }
+    if (s4 < K4) {
+      mfma_step<NCB, TR>(a0, bb, S, s4, acc);
+      a0 = a1;
+      ++s4;
+    }
+    if (KT) mfma_tail<NCB, TR>(a0, bb, S, s4, KT, acc);
+    return;
+  }
+  // a0, a1: the fragments of chunks s4 and s4 + 1
+  for (; s4 + 3 <= K4; s4 += 3) {
+    const v4f a2 = frag(s4 + 2);
     mfma_step<NCB, TR>(a0, bb, S, s4, acc);
-    a0 = ldg4u(afrag + (s4 + 2 < KC ? s4 + 2 : s4 + 1) * 256, lo);
+    a0 = frag(s4 + 3);
     mfma_step<NCB, TR>(a1, bb, S, s4 + 1, acc);
+    a1 = frag(s4 + 4);
+    mfma_step<NCB, TR>(a2, bb, S, s4 + 2, acc);
   }
   if (s4 < K4) {
-    const v4f a1 = KT ? ldg4u(afrag + (s4 + 1) * 256, lo) : a0;
+    const v4f a2 = frag(s4 + 2);
+    mfma_step<NCB, TR>(a0, bb, S, s4, acc);
+    a0 = a1;
+    a1 = a2;
+    ++s4;
+  }
+  if (s4 < K4) {
     mfma_step<NCB, TR>(a0, bb, S, s4, acc);
     a0 = a1;
     ++s4;
@@ -1056,7 +1087,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         // the older one, which then idles at the next barrier while the younger
         // finishes.  Raising the younger half's priority for the GEMM evens them.
         if (prio && w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-        gemm_rows<NCB, true, true>(Wf, hin, S, K4, g, j, lane, acc, KT);
+        gemm_rows<NCB, true, true, DIM == 2>(Wf, hin, S, K4, g, j, lane, acc, KT);
         __builtin_amdgcn_s_setprio(0);
         if (pde) add_bias_t<NCB, MP::NPB>(acc, bp + (l - 1) * Wp, w, j);
         else add_bias_t<NCB, MV::NPB>(acc, bp + (l - 1) * Wp, w, j);
@@ -1404,7 +1435,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
         {
           const float* WT = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)Wp * Wp + (size_t)w * 16 * Wp;
           if (prio && w >= (NW >> 1)) __builtin_amdgcn_s_setprio(2);
-          gemm_rows<NCB, true, true>(WT, bufG, S, K4, g, j, lane, acc, KT);
+          gemm_rows<NCB, true, true, DIM == 2>(WT, bufG, S, K4, g, j, lane, acc, KT);
           __builtin_amdgcn_s_setprio(0);
         }
       }
