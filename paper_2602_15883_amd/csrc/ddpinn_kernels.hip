@@ -1492,15 +1492,23 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
           const size_t zl = (size_t)(l - 1) * NCB * 256, zp = (size_t)(l - 2) * NCB * 256;
 #pragma unroll
           for (int hh = 0; hh < 2; ++hh) {
-            __syncthreads();
+            // this half's Zbar_l of both row blocks: the wave's own stash
+            // slots, so they are requested before the barrier (which only
+            // guards the LDS stacks)
             v4f t[NCBH];
-            // Zbar_l of this half
-            for (int r = 0; r < nrb; ++r) {
-              const float* st = stash_w + r * stash_rb + zl + (size_t)hh * NCBH * 256;
+            v4f tz[2][NCBH];
 #pragma unroll
-              for (int c = 0; c < NCBH; ++c) t[c] = ldg4u(st + c * 256, lo16);
-              store_fwd<NCBH>(bufG, S, t, w + r * NWV, g, j);
+            for (int r = 0; r < 2; ++r) {
+              if (r < nrb) {
+#pragma unroll
+                for (int c = 0; c < NCBH; ++c)
+                  tz[r][c] = ldg4u(stash_w + r * stash_rb + zl + ((size_t)hh * NCBH + c) * 256, lo16);
+              }
             }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+              if (r < nrb) store_fwd<NCBH>(bufG, S, tz[r], w + r * NWV, g, j);
             // H_{l-1} of this half, recomputed from z_{l-1}
             for (int r = 0; r < nrb; ++r) {
 #pragma unroll
