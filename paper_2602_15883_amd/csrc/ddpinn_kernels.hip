@@ -1558,19 +1558,37 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
       } else {
         // every block's Zbar_l and H_{l-1} fit in LDS together
         for (int l = H; l >= 2; --l) {
+          // the first block's Zbar_l and z_{l-1} come from the wave's own
+          // stash slots: in 2D they are requested before the barrier (which
+          // only guards the LDS stacks), so their latency overlaps the wait
+          // (the 3D kernels have no registers to hold them across it)
+          constexpr bool early = DIM == 2;
+          v4f zb[NCB];
+          if (early) {
+            if (nrb == 2) {
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) zb[cb] = ldg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16);
+            }
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(stash_w + ((l - 2) * NCB + cb) * 256, lo16);
+          }
           __syncthreads();
           // Zbar_l into LDS: the last block's from registers, the first's from the stash
           store_fwd<NCB>(bufG, S, acc, w + (nrb - 1) * NWV, g, j);
           if (nrb == 2) {
+            if (!early) {
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) acc[cb] = ldg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16);
-            store_fwd<NCB>(bufG, S, acc, w, g, j);
+              for (int cb = 0; cb < NCB; ++cb) zb[cb] = ldg4u(stash_w + ((l - 1) * NCB + cb) * 256, lo16);
+            }
+            store_fwd<NCB>(bufG, S, zb, w, g, j);
           }
           // h_{l-1} recomputed from z_{l-1}
           for (int r = 0; r < nrb; ++r) {
+            if (r > 0 || !early) {
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb)
-              zs[cb] = ldg4u(stash_w + r * stash_rb + ((l - 2) * NCB + cb) * 256, lo16);
+              for (int cb = 0; cb < NCB; ++cb)
+                zs[cb] = ldg4u(stash_w + r * stash_rb + ((l - 2) * NCB + cb) * 256, lo16);
+            }
             if (pde) act_store_bwd<DIM, NCB, M_PDE, ACT>(bufH, S2, zs, w + r * NWV, g, j);
             else act_store_bwd<DIM, NCB, M_VALUE, ACT>(bufH, S2, zs, w + r * NWV, g, j);
           }
@@ -1609,11 +1627,13 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
             }
           }
           if (ks) {
+            if (nrb == 2) {
+#pragma unroll
+              for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(stash_w + stash_rb + ((l - 2) * NCB + cb) * 256, lo16);
+            }
             __syncthreads();   // the halves are in LDS
             if (nrb == 2) {
               const int e = w + NWV;
-#pragma unroll
-              for (int cb = 0; cb < NCB; ++cb) zs[cb] = ldg4u(stash_w + stash_rb + ((l - 2) * NCB + cb) * 256, lo16);
 #pragma unroll
               for (int cb = 0; cb < NCB; ++cb)
                 acc[cb] = *reinterpret_cast<const v4f*>(part + (w * NCB + cb) * 256 + lane * 4) +
