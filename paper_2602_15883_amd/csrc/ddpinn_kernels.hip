@@ -952,7 +952,7 @@ __global__ __launch_bounds__(PBP == 1 ? 512 : 256) void step_kernel(const StepAr
   float* red = lds + L.red;
   float* part = lds + L.part;
   const int S = SS ? SS : L.S, S2 = L.S2;
-  // two row blocks beyond the eight waves (one-stack plan): their GEMMs are
+  // two row blocks beyond the eight waves (the plan with two stacks per tile): their GEMMs are
   // split over K between waves w and w + 2 (w < 2, the blocks' owners), and
   // summed by the owner from four LDS tiles
   const bool ks = RPW == 2 && !SPLIT && L.nparts == 4;
