@@ -1,7 +1,8 @@
 """Networks wider than 128 neurons: each wave of the step, query and exchange
 kernels then owns two 16-neuron row blocks (w and w + 8).  Cases span a wave
 mix of one and two blocks (W = 150: waves 0-1 hold two; W = 144 in 3D: wave 0),
-all waves with two (W = 192, 256), padding (W = 129 -> 144), both
+all waves with two (W = 192, 256), three and seven extra row blocks (W = 176,
+240), padding (W = 129 -> 144), both
 activations, the paper's cylinder networks (2D 6 x 150 and 3D 8 x 200, sine;
 sections 3.2-3.3, appendix B), the column-split LDS plan, several tiles per
 workgroup, the largest shape, and the limits."""
@@ -43,6 +44,8 @@ WIDE = [(2, 150, 6, "sin", 87),      # the paper's 2D-cylinder network shape
         (3, 200, 2, "tanh", 8201),   # split, > 1 tile per workgroup
         (2, 192, 8, "tanh", 50),     # split
         (2, 256, 2, "sin", 300),     # split, every wave two blocks
+        (2, 176, 3, "tanh", 2500),   # three extra row blocks, > 1 tile per workgroup
+        (3, 240, 2, "sin", 60),      # split, seven extra row blocks
         (3, 256, 16, "tanh", 40)]    # the largest shape: split plan at the LDS limit
 
 
