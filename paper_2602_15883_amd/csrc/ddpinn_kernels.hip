@@ -2024,7 +2024,7 @@ __device__ __forceinline__ void forward_tile(const Shape& sh, const float* fr, f
       const float* Wf = fr + sh.f_hid + (size_t)(l - 2) * 2 * Wp * Wp + (size_t)rb * 16 * Wp;
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[r][cb] = zero4();
-      gemm_rows<NCB>(Wf, bufH, S, K4, g, j, lane, acc[r], KT);
+      gemm_rows<NCB, false, false, RPW == 1>(Wf, bufH, S, K4, g, j, lane, acc[r], KT);
       add_bias<NCB, M::NPB>(acc[r], fr + sh.f_b + (l - 1) * Wp, rb, g);
     }
     __syncthreads();
