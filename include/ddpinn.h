@@ -112,6 +112,12 @@ typedef struct {
   int32_t ranges_per_wg;  /* launch knob: item ranges per persistent
                              workgroup when several workgroups share a
                              compute unit (taken in turn); 0 = 4, 1..64     */
+  int32_t guard_bytes;    /* memory-check mode: 0 = off; else a multiple of
+                             256 up to 1 MiB left after every region of the
+                             workspace and filled with a pattern at create;
+                             pinn_check_guards counts the bytes a kernel
+                             overwrote there.  The workspace grows by this
+                             much per region                                */
 } pinn_config;
 
 typedef struct {
@@ -224,6 +230,16 @@ pinn_status pinn_exchange(pinn_ctx *ctx, const pinn_face *faces, int32_t n_faces
  * first to the end of the last.
  */
 pinn_status pinn_kernel_time(pinn_ctx *ctx, double *total_ms, int64_t *launches);
+
+/*
+ * Memory check (test and debugging aid, not part of the method): with
+ * pinn_config.guard_bytes > 0, waits for `stream`, copies every guard zone
+ * of the workspace to the host and writes to *bad_bytes the number of bytes
+ * that no longer hold the fill pattern (0 when no kernel wrote outside its
+ * region).  With guard_bytes = 0 it writes 0.  Synchronizes; allocates a
+ * host buffer of guard_bytes.  PINN_E_INVAL for a NULL argument.
+ */
+pinn_status pinn_check_guards(pinn_ctx *ctx, int64_t *bad_bytes, void *stream);
 
 /*
  * Evaluation post-processing (section 3: stitching of local experts, the

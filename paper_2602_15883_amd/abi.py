@@ -33,7 +33,7 @@ PINN_Q_RESIDUAL = 3
 EXPORTS = ("pinn_num_params", "pinn_create", "pinn_step", "pinn_query_scratch_bytes",
            "pinn_query", "pinn_query_noalloc", "pinn_exchange", "pinn_refresh", "pinn_destroy",
            "pinn_get_launch_info", "pinn_last_error", "pinn_kernel_time",
-           "pinn_evaluate_scratch_bytes", "pinn_evaluate")
+           "pinn_evaluate_scratch_bytes", "pinn_evaluate", "pinn_check_guards")
 
 
 class PinnError(RuntimeError):
@@ -49,7 +49,7 @@ class PinnConfig(ctypes.Structure):
                 ("eps", c_float), ("tile_points", c_int32), ("blocks_per_cu", c_int32),
                 ("max_query_points", c_int64), ("comp_w", c_float * 3), ("clip_norm", c_float),
                 ("lr_factor", c_float), ("lr_interval", c_int32), ("gemm_priority_off", c_int32),
-                ("ranges_per_wg", c_int32)]
+                ("ranges_per_wg", c_int32), ("guard_bytes", c_int32)]
 
 
 class PinnSubdomain(ctypes.Structure):
@@ -102,6 +102,8 @@ def lib():
                                 POINTER(c_void_p), c_void_p]
     L.pinn_kernel_time.restype = c_int32
     L.pinn_kernel_time.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int64)]
+    L.pinn_check_guards.restype = c_int32
+    L.pinn_check_guards.argtypes = [c_void_p, POINTER(c_int64), c_void_p]
     L.pinn_evaluate_scratch_bytes.restype = c_size_t
     L.pinn_evaluate_scratch_bytes.argtypes = [c_void_p, c_int64, c_int32, c_int64]
     L.pinn_evaluate.restype = c_int32

@@ -85,7 +85,7 @@ class Context:
                  activation: str = "tanh", comp_w=None, clip_norm: float = 0.0,
                  lr_factor: float = 1.0, lr_interval: int = 0,
                  gemm_priority: bool = True, ranges_per_wg: int = 0,
-                 device=None, stream=None):
+                 device=None, stream=None, guard_bytes: int = 0):
         if not torch.cuda.is_available():
             raise RuntimeError("libddpinn needs a ROCm GPU (gfx950); none is visible")
         L = lib()
@@ -115,6 +115,7 @@ class Context:
         cfg.blocks_per_cu = blocks_per_cu
         cfg.gemm_priority_off = 0 if gemm_priority else 1
         cfg.ranges_per_wg = int(ranges_per_wg)
+        cfg.guard_bytes = int(guard_bytes)
         cfg.max_query_points = max_query_points
         self.cfg = cfg
         arr = (PinnSubdomain * self.n_sub)()
@@ -229,6 +230,13 @@ class Context:
         n = ctypes.c_int64(0)
         check(lib().pinn_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n)))
         return float(ms.value), int(n.value)
+
+    def check_guards(self, stream=None) -> int:
+        """Memory-check mode (guard_bytes > 0): bytes of the workspace's guard
+        zones that no longer hold their fill pattern (waits for the stream)."""
+        bad = ctypes.c_int64(0)
+        check(lib().pinn_check_guards(self._h, ctypes.byref(bad), _stream(stream)))
+        return int(bad.value)
 
     def evaluate(self, x: torch.Tensor, ref: torch.Tensor, snap_off, x_anc, stream=None):
         """Relative L2 errors [u_1..u_d, velocity, p] after stitching, master

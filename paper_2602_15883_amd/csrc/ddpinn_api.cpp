@@ -239,6 +239,10 @@ struct pinn_ctx {
   ReduceArgs rargs{};
   StepArgs sargs{};
   PrepArgs pargs{};
+  // memory-check mode: guard zones (offset, bytes) after each workspace region
+  std::vector<std::pair<size_t, size_t>> guards;
+  char* ws = nullptr;
+  int guard_bytes = 0;
   // kernel timing (PINN_TIME_KERNEL)
   std::vector<hipEvent_t> ev_start, ev_stop;
   int ev_used = 0;
@@ -320,6 +324,8 @@ static pinn_status validate(const pinn_config* cfg, const pinn_subdomain* subs) 
   if (cfg->gemm_priority_off != 0 && cfg->gemm_priority_off != 1)
     return fail(PINN_E_INVAL, "gemm_priority_off must be 0 or 1");
   if (cfg->ranges_per_wg < 0 || cfg->ranges_per_wg > 64) return fail(PINN_E_INVAL, "ranges_per_wg must be 0..64");
+  if (cfg->guard_bytes < 0 || cfg->guard_bytes > (1 << 20) || (cfg->guard_bytes & 255))
+    return fail(PINN_E_INVAL, "guard_bytes must be a multiple of 256 in [0, 1 MiB]");
   if (cfg->max_query_points < 0 || cfg->max_query_points > (int64_t)INT32_MAX)
     return fail(PINN_E_INVAL, "max_query_points out of range");
   if (cfg->flags & ~PINN_GRAPH) return fail(PINN_E_INVAL, "unknown config flags 0x%x", cfg->flags);
@@ -498,9 +504,19 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   xcap += 8LL * c->n_sub + 64;
   c->x_cap = (int)std::min<int64_t>(xcap, 1 << 24);
 
-  // workspace layout
+  // workspace layout (in memory-check mode each region is followed by a guard zone)
   size_t off = 0;
-  auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+  const size_t gb = (size_t)cfg->guard_bytes;
+  std::vector<std::pair<size_t, size_t>> guards;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align256(bytes);
+    if (gb) {
+      guards.emplace_back(off, gb);
+      off += gb;
+    }
+    return o;
+  };
   const size_t o_subs = take(sizeof(SubDev) * c->n_sub);
   const size_t o_items = take(sizeof(Item) * std::max(c->n_items, 1));
   const size_t o_wgb = take(sizeof(int32_t) * (c->n_ranges + 1));
@@ -601,6 +617,10 @@ pinn_status pinn_create(const pinn_config* cfg, const pinn_subdomain* subs, void
   if (!wgb_ps.empty()) HIPCHECK(hipMemcpyAsync(c->d_wgb_ps, wgb_ps.data(), sizeof(int32_t) * wgb_ps.size(), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(c->d_seg_ps, seg_ps.data(), sizeof(int32_t) * (c->n_sub + 1), hipMemcpyHostToDevice, s));
   HIPCHECK(hipMemcpyAsync(c->d_boxes, boxes.data(), sizeof(float) * 8 * c->n_sub, hipMemcpyHostToDevice, s));
+  c->guards = guards;
+  c->ws = ws;
+  c->guard_bytes = (int)gb;
+  for (const auto& gz : c->guards) HIPCHECK(hipMemsetAsync(ws + gz.first, 0xA5, gz.second, s));
 
   // kernel argument blocks
   c->pargs.sh = sh;
@@ -972,6 +992,22 @@ pinn_status pinn_kernel_time(pinn_ctx* c, double* total_ms, int64_t* launches) {
   *launches = c->ev_folded_n;
   c->ev_folded_ms = 0.0;
   c->ev_folded_n = 0;
+  return PINN_OK;
+}
+
+pinn_status pinn_check_guards(pinn_ctx* c, int64_t* bad_bytes, void* stream) {
+  g_err.clear();
+  if (!c || !bad_bytes) return fail(PINN_E_INVAL, "NULL argument");
+  *bad_bytes = 0;
+  if (c->guards.empty()) return PINN_OK;
+  HIPCHECK(hipStreamSynchronize((hipStream_t)stream));
+  std::vector<unsigned char> h((size_t)c->guard_bytes);
+  int64_t bad = 0;
+  for (const auto& gz : c->guards) {
+    HIPCHECK(hipMemcpy(h.data(), c->ws + gz.first, gz.second, hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < gz.second; ++k) bad += h[k] != 0xA5;
+  }
+  *bad_bytes = bad;
   return PINN_OK;
 }
 
