@@ -101,3 +101,30 @@ def test_guard_check_sees_a_host_write_and_rejects_bad_sizes(pkg):
     for gb in (100, 2 << 20, -256):
         with pytest.raises(pkg.PinnError):
             pkg.context_from_problem(pb, device="cuda", guard_bytes=gb)
+
+
+def test_routed_query_stays_in_its_scratch_and_output(pkg):
+    """The caller's query scratch and output buffers: a routed query of n
+    points writes only the first pinn_query_scratch_bytes(n) bytes of the
+    scratch and the first n rows of the output (tails filled with a pattern
+    stay intact), for sizes on both sides of the one-workgroup routing path."""
+    boxes, thetas = wl.serving_nets(seed=4, width=100, depth=3)
+    subs = [wl._sub(2, boxes[s][0], boxes[s][1], thetas[s]) for s in range(len(thetas))]
+    pb = wl.Problem("serve_guard", 2, 100, 3, 0.01, np.ones(6), 1e-3, subs)
+    ctx = pkg.context_from_problem(pb, device="cuda", graph=False)
+    try:
+        rng = np.random.default_rng(8)
+        for n in (1, 700, 8192, 8193, 50000):
+            x = torch.from_numpy(np.ascontiguousarray(wl.query_points(rng, n), dtype=np.float32)).cuda()
+            need = ctx.query_scratch_bytes(n)
+            scratch = torch.full((need + 256 + GUARD,), 0xA5, dtype=torch.uint8, device="cuda")
+            off = (-scratch.data_ptr()) % 256
+            used = off + need
+            out = torch.full((n + 64, 4), -7.0, dtype=torch.float32, device="cuda")
+            # the binding passes the whole tensor; the library must keep to `need`
+            ctx.query(x, sub=-1, what="uvpw", out=out[:n], scratch=scratch)
+            torch.cuda.synchronize()
+            assert int((scratch[used:] != 0xA5).sum()) == 0, f"scratch tail written, n={n}"
+            assert bool((out[n:] == -7.0).all()), f"output rows past n written, n={n}"
+    finally:
+        ctx.close()
