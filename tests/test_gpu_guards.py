@@ -128,3 +128,28 @@ def test_routed_query_stays_in_its_scratch_and_output(pkg):
             assert bool((out[n:] == -7.0).all()), f"output rows past n written, n={n}"
     finally:
         ctx.close()
+
+
+def test_exchange_writes_only_the_rows_of_its_faces(pkg):
+    """Ghost targets of the faces not exchanged, and the rows around each
+    exchanged face, keep their sentinel value."""
+    pb = wl.config3(2, width=64, depth=2, pde_range=(50, 100), n_obs=10, n_gh_face=30)
+    ctx = pkg.context_from_problem(pb, device="cuda", graph=False)
+    try:
+        faces = [(a, b, first, count) for a, s in enumerate(pb.subs) for (b, kind, first, count) in s.faces]
+        chosen = faces[::2]
+        targets = [torch.full((s.gh_x.shape[0], 3), 123.0, dtype=torch.float32, device="cuda")
+                   for s in pb.subs]
+        ctx.exchange(chosen, pb.x_anc, targets)
+        torch.cuda.synchronize()
+        for a, s in enumerate(pb.subs):
+            mask = np.zeros(s.gh_x.shape[0], dtype=bool)
+            for (fa, b, first, count) in chosen:
+                if fa == a:
+                    mask[first:first + count] = True
+            t = targets[a].cpu().numpy()
+            assert np.all(t[~mask] == 123.0), f"sub {a}: rows outside its exchanged faces written"
+            if mask.any():
+                assert np.all(t[mask] != 123.0), f"sub {a}: rows of an exchanged face left unwritten"
+    finally:
+        ctx.close()
